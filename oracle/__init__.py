@@ -1,0 +1,353 @@
+"""FP64 CPU oracle of the camera operator, its transpose, the edge-preserving
+regularizer and the reconstruction algorithm.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+benchmark's CPU-baseline leg.  The product package never imports it, and it
+never imports the product package (it shares only the seeded input
+generators of ``paper_1812_03358_amd.workloads``, which hold no arithmetic of
+the method).
+
+Pins: every function here is checked against something other than itself in
+``tests/test_oracle_*.py`` (closed forms, conjugate-plane focusing, library
+routines, brute force).  See the module docstrings of those tests.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ltm_oracle.c")
+_LIB = os.path.join(_HERE, "_build", "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle (portable x86-64, IEEE FP64, OpenMP)."""
+    os.makedirs(os.path.dirname(_LIB), exist_ok=True)
+    if (not force and os.path.exists(_LIB)
+            and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC)):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+           "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("pitch", ctypes.c_double)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("nu", ctypes.c_int32), ("nv", ctypes.c_int32),
+                ("mu", ctypes.c_int32), ("mv", ctypes.c_int32),
+                ("ru", ctypes.c_int32), ("rv", ctypes.c_int32),
+                ("samples", ctypes.c_int32),
+                ("pixel_pitch", ctypes.c_double),
+                ("f_main", ctypes.c_double), ("r_main", ctypes.c_double),
+                ("d_det", ctypes.c_double),
+                ("d_mla", ctypes.c_double), ("d_mla_det", ctypes.c_double),
+                ("f_mla", ctypes.c_double), ("r_mla", ctypes.c_double),
+                ("axes", ctypes.c_double * 9), ("lens", ctypes.c_double * 3)]
+
+
+def _lib_handle():
+    global _lib
+    with _lock:
+        if _lib is None:
+            lib = ctypes.CDLL(build())
+            dp = ctypes.POINTER(ctypes.c_double)
+            gp, cp = ctypes.POINTER(Grid), ctypes.POINTER(Camera)
+            lib.orc_trace.argtypes = [cp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, dp, dp]
+            lib.orc_trace.restype = ctypes.c_int
+            lib.orc_clip.argtypes = [gp, dp, dp, dp]
+            lib.orc_clip.restype = ctypes.c_int
+            lib.orc_project.argtypes = [gp, cp, ctypes.c_int, dp, dp, ctypes.c_int]
+            lib.orc_backproject.argtypes = [gp, cp, ctypes.c_int, dp, dp, ctypes.c_int]
+            lib.orc_project_pixels.argtypes = [gp, cp, dp, ctypes.POINTER(ctypes.c_int64),
+                                               ctypes.c_int64, dp, ctypes.c_int]
+            lib.orc_pixel.argtypes = [gp, cp, dp, ctypes.c_int, ctypes.c_int]
+            lib.orc_pixel.restype = ctypes.c_double
+            lib.orc_count_valid_rays.argtypes = [gp, cp, ctypes.c_int]
+            lib.orc_count_valid_rays.restype = ctypes.c_int64
+            _lib = lib
+    return _lib
+
+
+def default_threads() -> int:
+    n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def _grid(g: dict) -> Grid:
+    return Grid(g["nx"], g["ny"], g["nz"], 0, g["pitch"])
+
+
+def _cams(cams) -> ctypes.Array:
+    arr = (Camera * len(cams))()
+    for k, c in enumerate(cams):
+        arr[k] = Camera(c["kind"], c["det_nu"], c["det_nv"], c["mla_nu"], c["mla_nv"],
+                        c["rays_u"], c["rays_v"], c["samples"], c["pixel_pitch"],
+                        c["f_main"], c["r_main"], c["d_det"], c["d_mla"], c["d_mla_det"],
+                        c["f_mla"], c["r_mla"], (ctypes.c_double * 9)(*c["axes"]),
+                        (ctypes.c_double * 3)(*c["lens_center"]))
+    return arr
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def n_voxels(g: dict) -> int:
+    return g["nx"] * g["ny"] * g["nz"]
+
+
+def n_meas(cams) -> int:
+    return sum(c["det_nu"] * c["det_nv"] for c in cams)
+
+
+# --------------------------------------------------------------------------
+# rays
+# --------------------------------------------------------------------------
+def trace(cam: dict, iu: int, iv: int, ru: int, rv: int):
+    """(valid, O, w): the ray of pixel (iu, iv), angular sample (ru, rv) as it
+    leaves the main lens; O on the lens plane, w with w . e_z = 1."""
+    lib = _lib_handle()
+    O = np.zeros(3)
+    w = np.zeros(3)
+    c = _cams([cam])
+    v = lib.orc_trace(c, iu, iv, ru, rv, _dptr(O), _dptr(w))
+    return bool(v), O, w
+
+
+def clip(g: dict, O, w):
+    """(hit, z0, z1): camera-depth interval of the ray inside the grid box."""
+    lib = _lib_handle()
+    O = np.ascontiguousarray(O, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    zr = np.zeros(2)
+    gg = _grid(g)
+    hit = lib.orc_clip(ctypes.byref(gg), _dptr(O), _dptr(w), _dptr(zr))
+    return bool(hit), float(zr[0]), float(zr[1])
+
+
+def count_valid_rays(g: dict, cam: dict, threads: int | None = None) -> int:
+    lib = _lib_handle()
+    gg = _grid(g)
+    return int(lib.orc_count_valid_rays(ctypes.byref(gg), _cams([cam]),
+                                        threads or default_threads()))
+
+
+# --------------------------------------------------------------------------
+# A and A^T
+# --------------------------------------------------------------------------
+def project(g: dict, cams, x, threads: int | None = None) -> np.ndarray:
+    """y = A x (FP64), cameras concatenated, each image (nv, nu) flattened."""
+    lib = _lib_handle()
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1))
+    assert x.size == n_voxels(g)
+    y = np.zeros(n_meas(cams))
+    gg = _grid(g)
+    lib.orc_project(ctypes.byref(gg), _cams(cams), len(cams), _dptr(x), _dptr(y),
+                    threads or default_threads())
+    return y
+
+
+def backproject(g: dict, cams, y, threads: int | None = None) -> np.ndarray:
+    """x = A^T y (FP64), flattened (nz, ny, nx)."""
+    lib = _lib_handle()
+    y = np.ascontiguousarray(np.asarray(y, dtype=np.float64).reshape(-1))
+    assert y.size == n_meas(cams)
+    x = np.zeros(n_voxels(g))
+    gg = _grid(g)
+    lib.orc_backproject(ctypes.byref(gg), _cams(cams), len(cams), _dptr(y), _dptr(x),
+                        threads or default_threads())
+    return x
+
+
+def project_pixels(g: dict, cam: dict, x, pixels, threads: int | None = None) -> np.ndarray:
+    """y at the listed flat pixel indices of one camera (FP64)."""
+    lib = _lib_handle()
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1))
+    pix = np.ascontiguousarray(np.asarray(pixels, dtype=np.int64))
+    out = np.zeros(pix.size)
+    gg = _grid(g)
+    lib.orc_project_pixels(ctypes.byref(gg), _cams([cam]), _dptr(x),
+                           pix.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                           pix.size, _dptr(out), threads or default_threads())
+    return out
+
+
+# --------------------------------------------------------------------------
+# edge-preserving regularizer (the paper's R(x) = beta/2 sum_j sum_{l in N_j}
+# psi(x_j - x_l), N_j the 26 neighbours; neighbours outside the grid absent)
+# --------------------------------------------------------------------------
+PSI_QUADRATIC = 0
+PSI_HYPERBOLA = 1
+
+OFFSETS26 = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)
+             if (dz, dy, dx) != (0, 0, 0)]
+
+
+def psi(t, kind: int, delta: float):
+    t = np.asarray(t, dtype=np.float64)
+    if kind == PSI_QUADRATIC:
+        return 0.5 * t * t
+    return delta * delta * (np.sqrt(1.0 + (t / delta) ** 2) - 1.0)
+
+
+def dpsi(t, kind: int, delta: float):
+    t = np.asarray(t, dtype=np.float64)
+    if kind == PSI_QUADRATIC:
+        return t
+    return t / np.sqrt(1.0 + (t / delta) ** 2)
+
+
+def _shift_pairs(shape, off):
+    """Slices (a, b) so that vol[a] and vol[b] are neighbours at offset off."""
+    a, b = [], []
+    for d, o in zip(shape, off):
+        if o >= 0:
+            a.append(slice(0, d - o))
+            b.append(slice(o, d))
+        else:
+            a.append(slice(-o, d))
+            b.append(slice(0, d + o))
+    return tuple(a), tuple(b)
+
+
+def reg_value(x, shape, beta: float, kind: int, delta: float) -> float:
+    x = np.asarray(x, dtype=np.float64).reshape(shape)
+    total = 0.0
+    for off in OFFSETS26:
+        a, b = _shift_pairs(shape, off)
+        total += psi(x[a] - x[b], kind, delta).sum()
+    return 0.5 * beta * total
+
+
+def reg_grad(x, shape, beta: float, kind: int, delta: float) -> np.ndarray:
+    """dR/dx_j = beta sum_{l in N_j} psi'(x_j - x_l) (psi even, so each pair
+    appears twice in R)."""
+    x = np.asarray(x, dtype=np.float64).reshape(shape)
+    g = np.zeros(shape)
+    for off in OFFSETS26:
+        a, b = _shift_pairs(shape, off)
+        g[a] += dpsi(x[a] - x[b], kind, delta)
+    return (beta * g).reshape(-1)
+
+
+# --------------------------------------------------------------------------
+# reconstruction (the paper's reconstruction-algorithm table, FISTA with a
+# diagonal majorizer; all arithmetic FP64)
+# --------------------------------------------------------------------------
+class Solver:
+    """Penalized nonnegative least squares with per-camera gains.
+
+    Psi(x, gamma) = 1/2 ||A_1 x - y_1||^2_W1 + sum_{c>=2} 1/2 ||A_c x - g_c y_c||^2_Wc
+                    + nu ||x||_1 + R(x),  x >= 0.
+    The majorizer is D = diag(sum_c A_c^T W_c A_c 1) plus c_R * beta for the
+    regularizer (the paper writes 26 beta; c_R is a parameter here, 36 by
+    default, the largest eigenvalue of the 26-neighbour graph Laplacian).
+    Voxels with D + c_R beta = 0 get a zero step.
+    """
+
+    def __init__(self, g, cams, ys, ws=None, beta=0.0, psi_kind=PSI_QUADRATIC, delta=1.0,
+                 nu=0.0, c_r=36.0, momentum=True, gains=False, x0=None, threads=None,
+                 ops=None):
+        """ops: optional list of (forward, adjoint) callables, one per camera,
+        replacing the camera operators (used to pin the algorithm on explicit
+        matrices)."""
+        self.g, self.cams = g, list(cams)
+        self.shape = (g["nz"], g["ny"], g["nx"])
+        self.threads = threads
+        if ops is None:
+            ops = [((lambda v, c=c: project(g, [c], v, threads)),
+                    (lambda r, c=c: backproject(g, [c], r, threads))) for c in self.cams]
+        self.ops = ops
+        self.ys = [np.asarray(y, dtype=np.float64).reshape(-1) for y in ys]
+        self.ws = ([np.ones_like(y) for y in self.ys] if ws is None else
+                   [np.asarray(w, dtype=np.float64).reshape(-1) for w in ws])
+        self.beta, self.psi_kind, self.delta, self.nu = beta, psi_kind, delta, nu
+        self.momentum, self.gains = momentum, gains
+        N = n_voxels(g)
+        ones = np.ones(N)
+        D = np.zeros(N)
+        for (fwd, adj), w in zip(self.ops, self.ws):
+            D += adj(w * fwd(ones))
+        self.D = D
+        Dt = D + c_r * beta
+        self.dinv = np.where(Dt > 0, 1.0 / np.where(Dt > 0, Dt, 1.0), 0.0)
+        self.x = np.zeros(N) if x0 is None else np.asarray(x0, np.float64).reshape(-1).copy()
+        self.z = self.x.copy()
+        self.t = 1.0
+        self.gamma = [1.0] + [0.0 if gains else 1.0] * (len(self.cams) - 1)
+        self.rho = math.inf
+        self.n = 0
+
+    def residual(self, v) -> float:
+        num = den = 0.0
+        for k, ((fwd, _), y, w) in enumerate(zip(self.ops, self.ys, self.ws)):
+            p = fwd(v)
+            gam = self._gain(k, p) if self.gains else self.gamma[k]
+            num += float(np.sum(w * (p - gam * y) ** 2))
+            den += float(np.sum(w * (gam * y) ** 2))
+        return math.sqrt(num / den) if den > 0 else math.inf
+
+    def _gain(self, k, p):
+        if k == 0:
+            return 1.0
+        y, w = self.ys[k], self.ws[k]
+        return float(np.dot(y, w * p) / np.dot(y, w * y))
+
+    def step(self):
+        grad = np.zeros_like(self.z)
+        num = den = 0.0
+        for k, ((fwd, adj), y, w) in enumerate(zip(self.ops, self.ys, self.ws)):
+            p = fwd(self.z)
+            if self.gains:
+                self.gamma[k] = self._gain(k, p)
+            r = w * (p - self.gamma[k] * y)
+            num += float(np.sum(w * (p - self.gamma[k] * y) ** 2))
+            den += float(np.sum(w * (self.gamma[k] * y) ** 2))
+            grad += adj(r)
+        self.rho = math.sqrt(num / den) if den > 0 else math.inf
+        if self.beta != 0.0:
+            grad += reg_grad(self.z, self.shape, self.beta, self.psi_kind, self.delta)
+        t_next = 0.5 * (1.0 + math.sqrt(1.0 + 4.0 * self.t * self.t))
+        wv = np.maximum(self.z - self.dinv * grad, 0.0)
+        x_next = np.maximum(wv - self.nu, 0.0)
+        if self.momentum:
+            self.z = x_next + ((self.t - 1.0) / t_next) * (x_next - self.x)
+        else:
+            self.z = x_next
+        self.x = x_next
+        self.t = t_next
+        self.n += 1
+        return self.rho
+
+    def run(self, n_iter: int):
+        for _ in range(n_iter):
+            self.step()
+        return self.x
+
+    def objective(self, v=None) -> float:
+        v = self.x if v is None else v
+        total = 0.0
+        for k, ((fwd, _), y, w) in enumerate(zip(self.ops, self.ys, self.ws)):
+            p = fwd(v)
+            gam = self._gain(k, p) if self.gains else self.gamma[k]
+            total += 0.5 * float(np.sum(w * (p - gam * y) ** 2))
+        total += self.nu * float(np.sum(np.abs(v)))
+        if self.beta != 0.0:
+            total += reg_value(v, self.shape, self.beta, self.psi_kind, self.delta)
+        return total
