@@ -1,0 +1,222 @@
+/*
+ * ltm.h -- C ABI of the light-transport camera model library (libltm.so).
+ *
+ * The library computes, on an AMD MI355X (gfx950), the matrix-free camera
+ * operator y = A x of McGaffin, Chen, Fessler and Sick, "A practical light
+ * transport system model for chemiluminescence distribution reconstruction"
+ * (arXiv 1812.03358), its exact transpose x = A^T y, and the penalized
+ * nonnegative least-squares reconstruction of the paper's reconstruction
+ * section.
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named x, y, w, ws, ... are DEVICE pointers (hipMalloc'ed or
+ *     torch CUDA tensors).  Descriptors and parameter structs are host
+ *     memory.  Streams are hipStream_t passed as void* (NULL = null stream).
+ *   - The library never allocates device memory: every buffer, including
+ *     the workspace a plan needs, is provided by the caller.  Plans and
+ *     solvers own host memory only.
+ *   - Calls are asynchronous on the given stream unless stated otherwise.
+ *     Outputs are overwritten, never accumulated into.
+ *   - Layouts: a volume x is float32 [nz][ny][nx] (x fastest), voxel (i,j,k)
+ *     centred at ((i + 1/2 - nx/2) d, (j + 1/2 - ny/2) d, (k + 1/2 - nz/2) d)
+ *     in world millimetres (the voxel basis of the paper's object-model
+ *     section); y holds the cameras' images one after another, each
+ *     float32 [det_nv][det_nu] with u (the s axis) fastest (the paper stores
+ *     light fields column-major with s fastest).
+ *   - Every function returns an ltm_status.  On failure nothing has been
+ *     launched and ltm_last_error() returns a message (thread-local).  No C++
+ *     exception crosses this interface.
+ */
+#ifndef LTM_H
+#define LTM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LTM_ABI_VERSION 1u
+
+typedef enum ltm_status {
+    LTM_OK = 0,
+    LTM_ERR_INVALID = 1,      /* bad descriptor, size or argument */
+    LTM_ERR_DEVICE = 2,       /* a HIP call failed */
+    LTM_ERR_NUMERIC = 3,      /* non-finite value met by the solver */
+    LTM_ERR_WORKSPACE = 4,    /* workspace missing or too small */
+    LTM_ERR_UNSUPPORTED = 5   /* valid request the library does not implement */
+} ltm_status;
+
+enum { LTM_SINGLE_LENS = 0u, LTM_PLENOPTIC = 1u };
+enum { LTM_FORWARD = 0u, LTM_ADJOINT = 1u };
+
+/* Voxel grid centred at the world origin (object-model section: pillbox
+ * voxels of edge pitch_mm; here sampled by trilinear interpolation between
+ * voxel centres).  Each of nx, ny, nz must be at least 2. */
+typedef struct ltm_grid {
+    uint32_t nx, ny, nz, reserved;
+    double pitch_mm;
+} ltm_grid;
+
+/* One camera.  Optics follow the paper's camera-model section: a thin main
+ * lens (focal length f_main, aperture radius r_main) at camera depth 0, with
+ *   single lens: the detector at depth -d_det;
+ *   plenoptic:   a square microlens array at depth -d_mla (lenslets of
+ *                radius r_mla, focal length f_mla, pitch det_nu/mla_nu
+ *                pixels) and the detector d_mla_det behind it.
+ * Rays are traced from each pixel centre through rays_u x rays_v angular
+ * samples -- the centres of a grid over the aperture's bounding square
+ * (main lens for single-lens cameras, the pixel's own lenslet for plenoptic
+ * ones); samples outside the circular aperture, or a plenoptic ray that
+ * misses the main lens, are occluded but still count in the 1/R mean.
+ * Each ray is integrated with `samples` midpoint samples over its segment
+ * inside the grid.  Camera point (s,t,z) is world point
+ * lens_center + s e_s + t e_t + z e_z, axes = {e_s, e_t, e_z} (orthonormal,
+ * right-handed), and the scene is at z > 0. */
+typedef struct ltm_camera {
+    uint32_t kind;              /* LTM_SINGLE_LENS or LTM_PLENOPTIC */
+    uint32_t det_nu, det_nv;    /* detector pixels */
+    uint32_t mla_nu, mla_nv;    /* plenoptic only: lenslets; det_n* multiples */
+    uint32_t rays_u, rays_v;    /* angular samples per pixel, R = rays_u*rays_v <= 64 */
+    uint32_t samples;           /* S >= 1 */
+    double pixel_pitch_mm;
+    double f_main_mm, r_main_mm;
+    double d_det_mm;            /* single lens only */
+    double d_mla_mm, d_mla_det_mm, f_mla_mm, r_mla_mm;  /* plenoptic only */
+    double axes[9];
+    double lens_center_mm[3];
+} ltm_camera;
+
+/* How one camera's rays are grouped into workgroups.  A tile is a block of
+ * tile_u x tile_v lenslets (for single-lens cameras, blocks of
+ * block_u x block_v pixels play the lenslets' role).  Its pixels are split
+ * over `splits` workgroups; order 0 puts one lenslet's pixels on adjacent
+ * lanes, order 1 walks adjacent lanes across lenslets.  Each workgroup
+ * marches its rays through consecutive slabs of chunk_mm camera depth,
+ * staging the voxels the slab's rays touch in an LDS brick of at most
+ * brick_floats floats (a slab whose brick does not fit uses global memory).
+ * Tilings change speed only: every tiling computes the same samples. */
+typedef struct ltm_tiling {
+    uint32_t tile_u, tile_v;
+    uint32_t block_u, block_v;
+    uint32_t order;
+    uint32_t splits;
+    uint32_t brick_floats;      /* 0: no LDS staging */
+    uint32_t reserved;
+    double chunk_mm;
+} ltm_tiling;
+
+typedef struct ltm_plan ltm_plan;
+
+uint32_t ltm_abi_version(void);
+const char* ltm_last_error(void);
+
+/* Validate the descriptors and build a plan (host memory only).  Errors:
+ * LTM_ERR_INVALID for zero or too-small sizes, a detector that is not a
+ * multiple of the lenslet count, non-positive focal lengths, radii or
+ * distances, axes that are not a right-handed orthonormal frame, R > 64 or
+ * S = 0. */
+ltm_status ltm_plan_create(const ltm_grid* grid, const ltm_camera* cams, uint32_t n_cam,
+                           ltm_plan** out);
+void ltm_plan_destroy(ltm_plan* plan);
+
+/* N = nx*ny*nz voxels and M = total pixels over all cameras. */
+ltm_status ltm_plan_sizes(const ltm_plan* plan, uint64_t* n_voxels, uint64_t* n_meas);
+
+/* Device workspace the plan needs (tile and brick tables), in bytes. */
+ltm_status ltm_plan_workspace_bytes(const ltm_plan* plan, uint64_t* bytes);
+
+/* Bind a caller-owned device workspace and fill its tables on `stream`.  The
+ * workspace must stay valid while the plan is used.  Must be called before
+ * ltm_project / ltm_backproject, and again after ltm_plan_set_tiling. */
+ltm_status ltm_plan_bind_workspace(ltm_plan* plan, void* ws, uint64_t bytes, void* stream);
+
+ltm_status ltm_plan_get_tiling(const ltm_plan* plan, uint32_t direction, uint32_t camera,
+                               ltm_tiling* out);
+/* Replace one camera's tiling for one direction.  The plan becomes unbound:
+ * query the workspace size and bind again. */
+ltm_status ltm_plan_set_tiling(ltm_plan* plan, uint32_t direction, uint32_t camera,
+                               const ltm_tiling* tiling);
+
+/* Number of rays of one camera (over all pixels and angular samples) that are
+ * unoccluded and cross the grid; each carries `samples` valid samples.  Uses
+ * the plan's workspace and synchronizes the stream. */
+ltm_status ltm_plan_valid_rays(ltm_plan* plan, uint32_t camera, uint64_t* rays, void* stream);
+
+/* y = A x: ray integrals of the trilinear interpolant of x, averaged over
+ * each pixel's angular samples (measurement-formation section; radiance as a
+ * line integral through the object, object-model section).  x: N floats,
+ * y: M floats (overwritten).  FP32 arithmetic, per-pixel sums in FP64. */
+ltm_status ltm_project(ltm_plan* plan, const float* x, float* y, void* stream);
+
+/* x = A^T y with the same samples and weights as ltm_project (the adjoint
+ * the paper's adjoint-operations section requires).  y: M floats,
+ * x: N floats (zeroed, then accumulated with FP32 atomics). */
+ltm_status ltm_backproject(ltm_plan* plan, const float* y, float* x, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Reconstruction: the paper's reconstruction-algorithm table (FISTA with a
+ * diagonal majorizer) for
+ *   min_{x>=0} sum_c 1/2 ||A_c x - g_c y_c||^2_{W_c} + nu ||x||_1 + R(x),
+ * R(x) = beta/2 sum_j sum_{l in N_j} psi(x_j - x_l) over the 26 neighbours
+ * present in the grid, psi(t) = t^2/2 or delta^2 (sqrt(1 + (t/delta)^2) - 1).
+ * The majorizer is diag(sum_c A_c^T W_c A_c 1) + c_R beta (the paper uses
+ * 26 beta; 36 is the largest eigenvalue of the 26-neighbour Laplacian),
+ * with a zero step where it vanishes.  Gains g_1 = 1 and, when enabled,
+ * g_c = y_c^T W_c p_c / y_c^T W_c y_c (c >= 2); otherwise all gains are 1.
+ * Vectors are FP32; inner products, gains, the momentum scalar t and the
+ * residual are FP64 on the device. */
+enum { LTM_PSI_QUADRATIC = 0u, LTM_PSI_HYPERBOLA = 1u };
+
+typedef struct ltm_solver_params {
+    uint32_t momentum;          /* 1: FISTA, 0: projected gradient */
+    uint32_t gains;             /* 1: estimate g_c for c >= 2 */
+    uint32_t psi_kind;
+    uint32_t reserved;
+    double beta, delta, nu, c_r;
+} ltm_solver_params;
+
+typedef struct ltm_solver ltm_solver;
+
+/* Device workspace a solver needs: 4 volumes, 2 images and FP64 scalars. */
+ltm_status ltm_solver_workspace_bytes(const ltm_plan* plan, uint64_t* bytes);
+
+/* Create a solver on a bound plan.  y (M floats) and w (M floats, or NULL
+ * for W = I) must stay valid while the solver is used.  Computes the
+ * majorizer on `stream`.  The iterate starts at 0. */
+ltm_status ltm_solver_create(ltm_plan* plan, const ltm_solver_params* params,
+                             const float* y, const float* w, void* ws, uint64_t ws_bytes,
+                             void* stream, ltm_solver** out);
+void ltm_solver_destroy(ltm_solver* solver);
+
+/* Restart from x0 (N floats on the device, or NULL for zero): x = z = x0,
+ * t = 1, gains reset. */
+ltm_status ltm_solver_reset(ltm_solver* solver, const float* x0, void* stream);
+
+/* Run n_iter iterations.  Asynchronous; no host synchronization. */
+ltm_status ltm_solver_step(ltm_solver* solver, uint32_t n_iter, void* stream);
+
+/* Copy the current iterate x (N floats) into `x`. */
+ltm_status ltm_solver_get_x(const ltm_solver* solver, float* x, void* stream);
+
+/* Relative data residual of the last iteration, rho = ||p - g y||_W / ||g y||_W
+ * with p = A z at that iteration's extrapolated point, and the iteration
+ * count.  Synchronizes the stream.  Returns LTM_ERR_NUMERIC if rho is not
+ * finite. */
+ltm_status ltm_solver_residual(ltm_solver* solver, double* rho, uint32_t* iterations,
+                               void* stream);
+
+/* Relative data residual of the current iterate x itself (one extra
+ * projection).  Synchronizes the stream. */
+ltm_status ltm_solver_residual_x(ltm_solver* solver, double* rho, void* stream);
+
+/* Gradient of R at z added into g:  g += beta sum_{l in N_j} psi'(z_j - z_l).
+ * z, g: N floats on the device. */
+ltm_status ltm_reg_grad_add(const ltm_grid* grid, uint32_t psi_kind, double beta, double delta,
+                            const float* z, float* g, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LTM_H */

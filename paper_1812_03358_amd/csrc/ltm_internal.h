@@ -1,0 +1,114 @@
+// Internal types shared by the host plan code and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ltm.h"
+
+namespace ltm {
+
+constexpr int kThreads = 256;      // workgroup size of every ray kernel
+constexpr int kMaxRays = 64;       // R limit per pixel
+constexpr int kMaxBrickFloats = 16384;  // brick words (4 bytes)
+constexpr int kMaxLdsBytes = 65536;     // dynamic LDS of one march workgroup
+constexpr int kMaxRayList = 8192;       // valid rays one workgroup may own
+
+// Per-tile record: camera depth (relative to the anchor plane) where the
+// tile's first slab starts, and its number of slabs.
+struct TileRec {
+    float z_start;
+    int n_chunks;
+};
+
+// Per-(tile, slab) record: voxel box [lo, lo + dim) staged in LDS, or
+// lds == 0 when it does not fit (the slab then reads/writes global memory).
+struct BrickRec {
+    int lo[3];
+    int dim[3];
+    int lds;
+    float base;   // lo.x + dim.x * (lo.y + dim.y * lo.z): flat index of lo
+};
+
+// Everything a kernel needs about one camera, in FP32 except the FP64
+// main-aperture test.  Built on the host in FP64 and rounded once.
+//
+// A ray of pixel (iu, iv), angular sample (ru, rv) is written with
+//   cu = lenslet index + 1/2 - mu/2, du = pixel index + 1/2 - nu/2,
+//   g  = (2 ru + 1)/Ru - 1 (aperture grid cell centre in [-1, 1]);
+// its lateral position on the anchor plane (the camera-depth plane through
+// the grid centre) and its slope after the main lens are linear in them:
+//   sigma = Ac cu + Ad du + Ag g,   slope = Bc cu + Bd du + Bg g,
+// and likewise for t with (cv, dv, g_t).  In voxel-index coordinates the
+// ray is q(z') = qA + z' dq with z' the camera depth relative to the anchor,
+//   qA = CA + sigma Es + tau Et,   dq = slope_s Es + slope_t Et + Ez.
+struct CamDev {
+    int kind, nu, nv, mu, mv, ku, kv, ru, rv, S;
+    int n[3];
+    float Ac, Ad, Ag, Bc, Bd, Bg;
+    float CA[3], Es[3], Et[3], Ez[3];
+    float zlo;            // lens plane: z' >= zlo
+    float invR;
+    float inv_ru, inv_rv;
+    int need_aperture;    // plenoptic: FP64 main-lens test per ray
+    double Lc, Ld, Lg, r2;  // main-lens crossing s_L = Lc cu + Ld du + Lg g; r_main^2
+    // tiling
+    int tile_u, tile_v, order, splits;
+    int rotate;           // lanes start their aperture-sample loop at lane mod R
+    int items, items_per_split, tiles_u, tiles_v, n_tiles;
+    int brick_cap;        // LDS brick capacity in voxels (FP32 forward, FP64 adjoint)
+    int max_chunks;
+    float chunk;
+    const TileRec* tiles;
+    const BrickRec* bricks;
+    uint64_t y_off;
+};
+
+struct CamHost {
+    ltm_camera desc;
+    ltm_tiling tiling[2];
+    CamDev dev;                 // constants without table pointers / tiling
+    uint64_t npix;
+    uint64_t y_off;
+    // workspace offsets (bytes) of this camera's tables, per direction
+    uint64_t tiles_off[2], bricks_off[2];
+    int n_tiles[2], max_chunks[2];
+};
+
+}  // namespace ltm
+
+struct ltm_plan {
+    ltm_grid grid;
+    std::vector<ltm::CamHost> cams;
+    uint64_t n_vox = 0, n_meas = 0;
+    uint64_t ws_bytes = 0;
+    uint64_t counter_off = 0;   // 256-byte scratch word for ltm_plan_valid_rays
+    uint64_t accum_off = 0;     // N doubles: FP64 accumulator of the adjoint
+    char* ws = nullptr;
+    bool bound = false;
+};
+
+namespace ltm {
+
+// error reporting (thread-local message)
+ltm_status fail(ltm_status s, const std::string& msg);
+ltm_status hip_fail(hipError_t e, const char* what);
+void clear_error();
+
+// kernel launchers (ltm_project.hip)
+hipError_t launch_setup(const CamDev& c, int dir, hipStream_t s);
+hipError_t launch_project(const CamDev& c, const float* x, float* y, hipStream_t s);
+hipError_t launch_backproject(const CamDev& c, const float* y, double* x, hipStream_t s);
+hipError_t launch_fill64(double* p, uint64_t n, hipStream_t s);
+hipError_t launch_to_f32(const double* a, float* b, uint64_t n, hipStream_t s);
+hipError_t launch_fill(float* p, uint64_t n, float v, hipStream_t s);
+hipError_t launch_count(const CamDev& c, unsigned long long* counter, hipStream_t s);
+size_t march_lds_bytes(const CamDev& c, int dir);
+
+// the camera's constants with the tables of one direction bound
+CamDev bound_dev(const ltm_plan* p, const CamHost& c, int dir);
+
+}  // namespace ltm

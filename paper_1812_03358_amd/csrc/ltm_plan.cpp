@@ -1,0 +1,449 @@
+// Host side of the camera operator: descriptor validation, the FP64 ray
+// constants of each camera, tilings, workspace layout and the C ABI of
+// project / backproject.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "ltm_internal.h"
+
+namespace ltm {
+
+namespace {
+thread_local std::string g_err;
+
+double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+uint64_t align256(uint64_t v) { return (v + 255u) & ~uint64_t(255u); }
+
+// Lateral crossing of the main lens sL, slope after it u2 and position on
+// the anchor plane sigma = sL + dA u2, for one of s/t, as functions of the
+// lenslet-centre index cu, the pixel index du and the aperture sample g.
+// The camera chain (single lens: detector -> lens; plenoptic: detector ->
+// lenslet -> main lens) is linear in (cu, du, g) with no constant term, so
+// evaluating it at unit inputs gives its coefficients.
+struct Chain {
+    double sL, u2, sigma;
+};
+
+Chain chain(const ltm_camera& c, double dA, double cu, double du, double g)
+{
+    Chain r;
+    const double p = c.pixel_pitch_mm;
+    if (c.kind == LTM_SINGLE_LENS) {
+        const double a = c.r_main_mm * g;              // aperture sample on the lens
+        const double sd = du * p;                       // pixel centre
+        const double u = (a - sd) / c.d_det_mm;         // propagation D
+        r.u2 = u - a / c.f_main_mm;                     // thin-lens refraction
+        r.sL = a;
+    } else {
+        const double P = (double)(c.det_nu / c.mla_nu) * p;  // lenslet pitch
+        const double cm = cu * P;                       // lenslet centre
+        const double a = cm + c.r_mla_mm * g;           // sample on the lenslet
+        const double sd = du * p;
+        const double u = (a - sd) / c.d_mla_det_mm;     // detector -> MLA
+        const double u1 = u - (a - cm) / c.f_mla_mm;    // lenslet refraction
+        r.sL = a + u1 * c.d_mla_mm;                     // MLA -> main lens
+        r.u2 = u1 - r.sL / c.f_main_mm;                 // main-lens refraction
+    }
+    r.sigma = r.sL + dA * r.u2;
+    return r;
+}
+
+ltm_status validate(const ltm_grid* g, const ltm_camera* cams, uint32_t n_cam)
+{
+    if (!g || !cams) return fail(LTM_ERR_INVALID, "null descriptor");
+    if (n_cam == 0) return fail(LTM_ERR_INVALID, "no cameras");
+    if (g->nx < 2 || g->ny < 2 || g->nz < 2)
+        return fail(LTM_ERR_INVALID, "grid needs at least 2 voxels per axis");
+    if ((uint64_t)g->nx * g->ny * g->nz > (1ull << 31))
+        return fail(LTM_ERR_INVALID, "grid larger than 2^31 voxels");
+    if (!(g->pitch_mm > 0.0) || !std::isfinite(g->pitch_mm))
+        return fail(LTM_ERR_INVALID, "grid pitch must be positive");
+    for (uint32_t i = 0; i < n_cam; ++i) {
+        const ltm_camera& c = cams[i];
+        const std::string who = "camera " + std::to_string(i) + ": ";
+        if (c.kind != LTM_SINGLE_LENS && c.kind != LTM_PLENOPTIC)
+            return fail(LTM_ERR_INVALID, who + "unknown kind");
+        if (c.det_nu == 0 || c.det_nv == 0) return fail(LTM_ERR_INVALID, who + "empty detector");
+        if ((uint64_t)c.det_nu * c.det_nv > (1ull << 30))
+            return fail(LTM_ERR_INVALID, who + "detector larger than 2^30 pixels");
+        if (c.rays_u == 0 || c.rays_v == 0 || c.rays_u * c.rays_v > (uint32_t)kMaxRays)
+            return fail(LTM_ERR_INVALID, who + "need 1 <= rays_u*rays_v <= 64");
+        if (c.samples == 0 || c.samples > (1u << 20))
+            return fail(LTM_ERR_INVALID, who + "need 1 <= samples <= 2^20");
+        if (!(c.pixel_pitch_mm > 0) || !(c.f_main_mm > 0) || !(c.r_main_mm > 0))
+            return fail(LTM_ERR_INVALID, who + "pitch, focal length and radius must be positive");
+        if (c.kind == LTM_SINGLE_LENS) {
+            if (!(c.d_det_mm > 0)) return fail(LTM_ERR_INVALID, who + "d_det must be positive");
+        } else {
+            if (c.mla_nu == 0 || c.mla_nv == 0 || c.det_nu % c.mla_nu || c.det_nv % c.mla_nv)
+                return fail(LTM_ERR_INVALID, who + "detector must be a multiple of the lenslet count");
+            if (!(c.d_mla_mm > 0) || !(c.d_mla_det_mm > 0) || !(c.f_mla_mm > 0) || !(c.r_mla_mm > 0))
+                return fail(LTM_ERR_INVALID, who + "lenslet distances, focal length and radius must be positive");
+        }
+        const double* e = c.axes;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                const double d = dot3(e + 3 * a, e + 3 * b) - (a == b ? 1.0 : 0.0);
+                if (!(std::fabs(d) < 1e-9)) return fail(LTM_ERR_INVALID, who + "axes not orthonormal");
+            }
+        const double cx[3] = {e[1] * e[5] - e[2] * e[4], e[2] * e[3] - e[0] * e[5],
+                              e[0] * e[4] - e[1] * e[3]};
+        if (!(dot3(cx, e + 6) > 0.999999)) return fail(LTM_ERR_INVALID, who + "axes not right-handed");
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(c.lens_center_mm[a])) return fail(LTM_ERR_INVALID, who + "bad lens centre");
+    }
+    return LTM_OK;
+}
+
+ltm_status check_tiling(const ltm_camera& c, const ltm_tiling& t)
+{
+    if (t.tile_u == 0 || t.tile_v == 0 || t.splits == 0)
+        return fail(LTM_ERR_INVALID, "tiling sizes must be positive");
+    if (c.kind == LTM_SINGLE_LENS && (t.block_u == 0 || t.block_v == 0))
+        return fail(LTM_ERR_INVALID, "single-lens tiling needs block sizes");
+    if (t.order > 3) return fail(LTM_ERR_INVALID, "tiling order must be 0..3");
+    if (t.brick_floats > (uint32_t)kMaxBrickFloats)
+        return fail(LTM_ERR_INVALID, "brick larger than 64 KiB of LDS");
+    if (!(t.chunk_mm > 0) || !std::isfinite(t.chunk_mm))
+        return fail(LTM_ERR_INVALID, "chunk_mm must be positive");
+    const uint64_t ku = c.kind == LTM_PLENOPTIC ? c.det_nu / c.mla_nu : t.block_u;
+    const uint64_t kv = c.kind == LTM_PLENOPTIC ? c.det_nv / c.mla_nv : t.block_v;
+    const uint64_t items = (uint64_t)t.tile_u * t.tile_v * ku * kv;
+    const uint64_t per = (items + t.splits - 1) / t.splits;
+    if (per == 0 || per > 8ull * kThreads)
+        return fail(LTM_ERR_INVALID, "a workgroup may own at most 2048 pixels of a tile");
+    const uint64_t R = (uint64_t)c.rays_u * c.rays_v;
+    if (per * R > (uint64_t)kMaxRayList)
+        return fail(LTM_ERR_INVALID, "a workgroup may own at most 8192 rays (pixels x R)");
+    const uint64_t lds = ((per * R * 4 + 15) & ~15ull) + ((per * 8 + 15) & ~15ull) +
+                         (uint64_t)t.brick_floats * 4;
+    if (lds > (uint64_t)kMaxLdsBytes)
+        return fail(LTM_ERR_INVALID, "ray list, pixel sums and brick exceed 64 KiB of LDS");
+    if (items > (1ull << 30)) return fail(LTM_ERR_INVALID, "tile too large");
+    return LTM_OK;
+}
+
+ltm_tiling default_tiling(const ltm_grid& g, const ltm_camera& c, int dir)
+{
+    ltm_tiling t{};
+    t.tile_u = t.tile_v = 1;
+    t.block_u = t.block_v = 16;
+    t.order = 0;
+    t.splits = 1;
+    t.brick_floats = 8192;
+    t.chunk_mm = 64.0 * g.pitch_mm;
+    const uint32_t R = c.rays_u * c.rays_v;
+    if (c.kind == LTM_SINGLE_LENS)
+        while (t.block_u > 1 && (uint64_t)t.block_u * t.block_v * R > 4096u) {
+            t.block_u /= 2;
+            t.block_v /= 2;
+        }
+    if (c.kind == LTM_PLENOPTIC && dir == LTM_FORWARD) {
+        // a lenslet's rays with one aperture sample form a bundle a fraction
+        // of a voxel wide: lenslet-major lanes read the same LDS words
+        // (broadcast), and 2x2 lenslets split 4 ways keep 1024 rays per group
+        t.tile_u = t.tile_v = 2;
+        t.order = 2;
+        t.splits = 4;
+        t.brick_floats = 4096;
+    }
+    if (c.kind == LTM_PLENOPTIC && dir == LTM_ADJOINT) {
+        // adjacent lanes in different lenslets: a bundle's rays converge on
+        // the same voxels, which would serialize LDS atomics within a wave
+        t.tile_u = t.tile_v = 4;
+        t.order = 3;
+        t.chunk_mm = 16.0 * g.pitch_mm;
+        const uint32_t k = (c.det_nu / c.mla_nu) * (c.det_nv / c.mla_nv);
+        t.splits = 1;
+        while (16u * k / (t.splits * 2) >= 64u) t.splits *= 2;
+    }
+    // shrink until the ray list, pixel sums and brick fit one workgroup
+    for (int guard = 0; guard < 64 && check_tiling(c, t) != LTM_OK; ++guard) {
+        if (t.brick_floats > 2048)
+            t.brick_floats /= 2;
+        else
+            t.splits *= 2;
+    }
+    clear_error();
+    return t;
+}
+
+// Fill the FP32/FP64 ray constants of one camera (tiling-independent part).
+void camera_constants(const ltm_grid& g, const ltm_camera& c, CamDev& d)
+{
+    std::memset(&d, 0, sizeof(d));
+    d.kind = (int)c.kind;
+    d.nu = (int)c.det_nu;
+    d.nv = (int)c.det_nv;
+    d.ru = (int)c.rays_u;
+    d.rv = (int)c.rays_v;
+    d.S = (int)c.samples;
+    d.n[0] = (int)g.nx;
+    d.n[1] = (int)g.ny;
+    d.n[2] = (int)g.nz;
+    const double* es = c.axes;
+    const double* et = c.axes + 3;
+    const double* ez = c.axes + 6;
+    const double* L = c.lens_center_mm;
+    // anchor plane: the camera-depth plane through the grid centre (origin)
+    const double dA = -dot3(L, ez);
+    const Chain k_c = chain(c, dA, 1, 0, 0), k_d = chain(c, dA, 0, 1, 0), k_g = chain(c, dA, 0, 0, 1);
+    const bool pl = c.kind == LTM_PLENOPTIC;
+    d.Ac = pl ? (float)k_c.sigma : 0.0f;
+    d.Bc = pl ? (float)k_c.u2 : 0.0f;
+    d.Ad = (float)k_d.sigma;
+    d.Bd = (float)k_d.u2;
+    d.Ag = (float)k_g.sigma;
+    d.Bg = (float)k_g.u2;
+    const double nn[3] = {(double)g.nx, (double)g.ny, (double)g.nz};
+    for (int a = 0; a < 3; ++a) {
+        d.CA[a] = (float)((L[a] + dA * ez[a]) / g.pitch_mm + 0.5 * nn[a] - 0.5);
+        d.Es[a] = (float)(es[a] / g.pitch_mm);
+        d.Et[a] = (float)(et[a] / g.pitch_mm);
+        d.Ez[a] = (float)(ez[a] / g.pitch_mm);
+    }
+    d.zlo = (float)(-dA);
+    d.invR = (float)(1.0 / ((double)c.rays_u * c.rays_v));
+    d.inv_ru = (float)(1.0 / c.rays_u);
+    d.inv_rv = (float)(1.0 / c.rays_v);
+    d.need_aperture = pl ? 1 : 0;
+    d.Lc = pl ? k_c.sL : 0.0;
+    d.Ld = k_d.sL;
+    d.Lg = k_g.sL;
+    d.r2 = c.r_main_mm * c.r_main_mm;
+}
+
+// Tiling-dependent fields.
+void apply_tiling(const ltm_grid& g, const ltm_camera& c, const ltm_tiling& t, CamDev& d,
+                  int& n_tiles, int& max_chunks)
+{
+    if (c.kind == LTM_PLENOPTIC) {
+        d.ku = (int)(c.det_nu / c.mla_nu);
+        d.kv = (int)(c.det_nv / c.mla_nv);
+        d.mu = (int)c.mla_nu;
+        d.mv = (int)c.mla_nv;
+    } else {
+        d.ku = (int)t.block_u;
+        d.kv = (int)t.block_v;
+        d.mu = (int)((c.det_nu + t.block_u - 1) / t.block_u);
+        d.mv = (int)((c.det_nv + t.block_v - 1) / t.block_v);
+    }
+    d.tile_u = (int)t.tile_u;
+    d.tile_v = (int)t.tile_v;
+    d.order = (int)t.order;
+    d.rotate = (t.order & 2) ? 0 : 1;
+    d.splits = (int)t.splits;
+    d.items = d.tile_u * d.tile_v * d.ku * d.kv;
+    d.items_per_split = (d.items + d.splits - 1) / d.splits;
+    d.tiles_u = (d.mu + d.tile_u - 1) / d.tile_u;
+    d.tiles_v = (d.mv + d.tile_v - 1) / d.tile_v;
+    d.n_tiles = d.tiles_u * d.tiles_v * d.splits;
+    d.brick_cap = (int)t.brick_floats;
+    d.chunk = (float)t.chunk_mm;
+    const double diag = g.pitch_mm * std::sqrt((double)g.nx * g.nx + (double)g.ny * g.ny +
+                                               (double)g.nz * g.nz);
+    d.max_chunks = (int)std::ceil(diag / t.chunk_mm) + 2;
+    n_tiles = d.n_tiles;
+    max_chunks = d.max_chunks;
+}
+
+void layout(ltm_plan* p)
+{
+    uint64_t off = 0;
+    for (auto& c : p->cams) {
+        for (int dir = 0; dir < 2; ++dir) {
+            CamDev tmp = c.dev;
+            apply_tiling(p->grid, c.desc, c.tiling[dir], tmp, c.n_tiles[dir], c.max_chunks[dir]);
+            c.tiles_off[dir] = off;
+            off = align256(off + sizeof(TileRec) * (uint64_t)c.n_tiles[dir]);
+            c.bricks_off[dir] = off;
+            off = align256(off + sizeof(BrickRec) * (uint64_t)c.n_tiles[dir] * c.max_chunks[dir]);
+        }
+    }
+    p->counter_off = off;
+    off += 256;
+    p->accum_off = off;
+    off = align256(off + sizeof(double) * p->n_vox);
+    p->ws_bytes = off;
+}
+
+}  // namespace
+
+ltm_status fail(ltm_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+ltm_status hip_fail(hipError_t e, const char* what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return LTM_ERR_DEVICE;
+}
+
+void clear_error() { g_err.clear(); }
+
+CamDev bound_dev(const ltm_plan* p, const CamHost& c, int dir)
+{
+    CamDev d = c.dev;
+    int nt, mc;
+    apply_tiling(p->grid, c.desc, c.tiling[dir], d, nt, mc);
+    if (dir == LTM_ADJOINT) d.brick_cap /= 2;   // FP64 brick in the same LDS budget
+    d.tiles = reinterpret_cast<const TileRec*>(p->ws + c.tiles_off[dir]);
+    d.bricks = reinterpret_cast<const BrickRec*>(p->ws + c.bricks_off[dir]);
+    d.y_off = c.y_off;
+    return d;
+}
+
+const char* last_error() { return g_err.c_str(); }
+
+}  // namespace ltm
+
+using namespace ltm;
+
+extern "C" {
+
+uint32_t ltm_abi_version(void) { return LTM_ABI_VERSION; }
+
+const char* ltm_last_error(void) { return ltm::last_error(); }
+
+ltm_status ltm_plan_create(const ltm_grid* grid, const ltm_camera* cams, uint32_t n_cam,
+                           ltm_plan** out)
+{
+    if (!out) return fail(LTM_ERR_INVALID, "null output pointer");
+    *out = nullptr;
+    ltm_status s = validate(grid, cams, n_cam);
+    if (s != LTM_OK) return s;
+    ltm_plan* p = new (std::nothrow) ltm_plan();
+    if (!p) return fail(LTM_ERR_INVALID, "out of host memory");
+    p->grid = *grid;
+    p->n_vox = (uint64_t)grid->nx * grid->ny * grid->nz;
+    uint64_t yoff = 0;
+    for (uint32_t i = 0; i < n_cam; ++i) {
+        CamHost c{};
+        c.desc = cams[i];
+        for (int dir = 0; dir < 2; ++dir) c.tiling[dir] = default_tiling(*grid, cams[i], dir);
+        camera_constants(*grid, cams[i], c.dev);
+        c.npix = (uint64_t)cams[i].det_nu * cams[i].det_nv;
+        c.y_off = yoff;
+        yoff += c.npix;
+        p->cams.push_back(c);
+    }
+    p->n_meas = yoff;
+    layout(p);
+    clear_error();
+    *out = p;
+    return LTM_OK;
+}
+
+void ltm_plan_destroy(ltm_plan* plan) { delete plan; }
+
+ltm_status ltm_plan_sizes(const ltm_plan* p, uint64_t* n_voxels, uint64_t* n_meas)
+{
+    if (!p) return fail(LTM_ERR_INVALID, "null plan");
+    if (n_voxels) *n_voxels = p->n_vox;
+    if (n_meas) *n_meas = p->n_meas;
+    return LTM_OK;
+}
+
+ltm_status ltm_plan_workspace_bytes(const ltm_plan* p, uint64_t* bytes)
+{
+    if (!p || !bytes) return fail(LTM_ERR_INVALID, "null argument");
+    *bytes = p->ws_bytes;
+    return LTM_OK;
+}
+
+ltm_status ltm_plan_bind_workspace(ltm_plan* p, void* ws, uint64_t bytes, void* stream)
+{
+    if (!p) return fail(LTM_ERR_INVALID, "null plan");
+    if (!ws || bytes < p->ws_bytes)
+        return fail(LTM_ERR_WORKSPACE, "workspace of " + std::to_string(p->ws_bytes) +
+                                           " bytes required");
+    if (reinterpret_cast<uintptr_t>(ws) % 256)
+        return fail(LTM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    p->ws = static_cast<char*>(ws);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (auto& c : p->cams)
+        for (int dir = 0; dir < 2; ++dir) {
+            const CamDev d = bound_dev(p, c, dir);
+            hipError_t e = launch_setup(d, dir, s);
+            if (e != hipSuccess) return hip_fail(e, "tile setup");
+        }
+    p->bound = true;
+    clear_error();
+    return LTM_OK;
+}
+
+ltm_status ltm_plan_get_tiling(const ltm_plan* p, uint32_t dir, uint32_t cam, ltm_tiling* out)
+{
+    if (!p || !out) return fail(LTM_ERR_INVALID, "null argument");
+    if (dir > 1 || cam >= p->cams.size()) return fail(LTM_ERR_INVALID, "bad direction or camera");
+    *out = p->cams[cam].tiling[dir];
+    return LTM_OK;
+}
+
+ltm_status ltm_plan_set_tiling(ltm_plan* p, uint32_t dir, uint32_t cam, const ltm_tiling* t)
+{
+    if (!p || !t) return fail(LTM_ERR_INVALID, "null argument");
+    if (dir > 1 || cam >= p->cams.size()) return fail(LTM_ERR_INVALID, "bad direction or camera");
+    ltm_status s = check_tiling(p->cams[cam].desc, *t);
+    if (s != LTM_OK) return s;
+    p->cams[cam].tiling[dir] = *t;
+    layout(p);
+    p->bound = false;
+    p->ws = nullptr;
+    clear_error();
+    return LTM_OK;
+}
+
+ltm_status ltm_plan_valid_rays(ltm_plan* p, uint32_t cam, uint64_t* rays, void* stream)
+{
+    if (!p || !rays) return fail(LTM_ERR_INVALID, "null argument");
+    if (cam >= p->cams.size()) return fail(LTM_ERR_INVALID, "bad camera");
+    if (!p->bound) return fail(LTM_ERR_WORKSPACE, "plan has no bound workspace");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto* ctr = reinterpret_cast<unsigned long long*>(p->ws + p->counter_off);
+    hipError_t e = hipMemsetAsync(ctr, 0, sizeof(unsigned long long), s);
+    if (e == hipSuccess) e = launch_count(bound_dev(p, p->cams[cam], LTM_FORWARD), ctr, s);
+    unsigned long long h = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, ctr, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "count rays");
+    *rays = h;
+    return LTM_OK;
+}
+
+ltm_status ltm_project(ltm_plan* p, const float* x, float* y, void* stream)
+{
+    if (!p || !x || !y) return fail(LTM_ERR_INVALID, "null argument");
+    if (!p->bound) return fail(LTM_ERR_WORKSPACE, "plan has no bound workspace");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (auto& c : p->cams) {
+        hipError_t e = launch_project(bound_dev(p, c, LTM_FORWARD), x, y, s);
+        if (e != hipSuccess) return hip_fail(e, "project");
+    }
+    return LTM_OK;
+}
+
+ltm_status ltm_backproject(ltm_plan* p, const float* y, float* x, void* stream)
+{
+    if (!p || !x || !y) return fail(LTM_ERR_INVALID, "null argument");
+    if (!p->bound) return fail(LTM_ERR_WORKSPACE, "plan has no bound workspace");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* acc = reinterpret_cast<double*>(p->ws + p->accum_off);
+    hipError_t e = launch_fill64(acc, p->n_vox, s);
+    if (e != hipSuccess) return hip_fail(e, "zero accumulator");
+    for (auto& c : p->cams) {
+        e = launch_backproject(bound_dev(p, c, LTM_ADJOINT), y, acc, s);
+        if (e != hipSuccess) return hip_fail(e, "backproject");
+    }
+    e = launch_to_f32(acc, x, p->n_vox, s);
+    if (e != hipSuccess) return hip_fail(e, "convert");
+    return LTM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,664 @@
+// gfx950 kernels of the camera operator y = A x and its transpose.
+//
+// A ray of a pixel is traced back through the camera's lenses (the affine
+// propagation and thin-lens maps of the paper's optics table, composed per
+// its camera-model section), clipped to the voxel box and integrated with S
+// midpoint samples of the trilinear interpolant (line-integral radiance of
+// the object-model section).  The pixel value is the mean over its R
+// angular samples (measurement-formation section).  The transpose uses the
+// same samples and weights, so it is the exact adjoint (adjoint-operations
+// section).
+//
+// Work decomposition (not the paper's: its separable filtering kernels are
+// replaced by a ray march): one workgroup owns a tile of pixels; it walks
+// the tile's rays through slabs of camera depth, staging the voxels a slab
+// touches in an LDS brick (forward: gather from LDS; adjoint: LDS float
+// atomics, then one global atomic flush per brick voxel).  The brick of
+// every (tile, slab) is computed once per plan by k_setup.
+#include "ltm_internal.h"
+
+#include <cfloat>
+
+namespace ltm {
+
+namespace {
+
+struct Ray {
+    float qA[3], dq[3];
+    float z0, z1, h, inv_h, w;
+};
+
+// Pixel of one work item of a tile, or false for a ragged item.
+__device__ __forceinline__ bool item_pixel(const CamDev& c, int tile, int item, int& iu, int& iv)
+{
+    if (item >= c.items_per_split) return false;
+    const int split = tile % c.splits;
+    const int blk = tile / c.splits;
+    const int it = split * c.items_per_split + item;
+    if (it >= c.items) return false;
+    const int tu = blk % c.tiles_u, tv = blk / c.tiles_u;
+    const int tl = c.tile_u * c.tile_v, kk = c.ku * c.kv;
+    int lid, pid;
+    if ((c.order & 1) == 0) {
+        lid = it / kk;
+        pid = it - lid * kk;
+    } else {
+        pid = it / tl;
+        lid = it - pid * tl;
+    }
+    const int lu = tu * c.tile_u + lid % c.tile_u;
+    const int lv = tv * c.tile_v + lid / c.tile_u;
+    if (lu >= c.mu || lv >= c.mv) return false;
+    iu = lu * c.ku + pid % c.ku;
+    iv = lv * c.kv + pid / c.ku;
+    return iu < c.nu && iv < c.nv;
+}
+
+// Geometry of ray (ru, rv) of pixel (iu, iv).  Returns false when the ray is
+// occluded (aperture grid sample outside the unit disc, or a plenoptic ray
+// missing the main lens -- decided in FP64) or misses the voxel box.
+__device__ __forceinline__ bool make_ray(const CamDev& c, int iu, int iv, int ru, int rv, Ray& r)
+{
+    const int a = 2 * ru + 1 - c.ru, b = 2 * rv + 1 - c.rv;
+    if ((long long)a * a * c.rv * c.rv + (long long)b * b * c.ru * c.ru >
+        (long long)c.ru * c.ru * c.rv * c.rv)
+        return false;
+    const float gs = (float)a / (float)c.ru;
+    const float gt = (float)b / (float)c.rv;
+    float cu = 0.0f, cv = 0.0f;
+    if (c.kind == LTM_PLENOPTIC) {
+        cu = (float)(iu / c.ku) + 0.5f - 0.5f * (float)c.mu;
+        cv = (float)(iv / c.kv) + 0.5f - 0.5f * (float)c.mv;
+    }
+    const float du = (float)iu + 0.5f - 0.5f * (float)c.nu;
+    const float dv = (float)iv + 0.5f - 0.5f * (float)c.nv;
+    if (c.need_aperture) {
+        const double sL = c.Lc * (double)cu + c.Ld * (double)du + c.Lg * (double)gs;
+        const double tL = c.Lc * (double)cv + c.Ld * (double)dv + c.Lg * (double)gt;
+        if (sL * sL + tL * tL > c.r2) return false;
+    }
+    const float sig = fmaf(c.Ac, cu, fmaf(c.Ad, du, c.Ag * gs));
+    const float tau = fmaf(c.Ac, cv, fmaf(c.Ad, dv, c.Ag * gt));
+    const float us = fmaf(c.Bc, cu, fmaf(c.Bd, du, c.Bg * gs));
+    const float vs = fmaf(c.Bc, cv, fmaf(c.Bd, dv, c.Bg * gt));
+    float zl = c.zlo, zh = FLT_MAX;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        r.qA[k] = fmaf(sig, c.Es[k], fmaf(tau, c.Et[k], c.CA[k]));
+        r.dq[k] = fmaf(us, c.Es[k], fmaf(vs, c.Et[k], c.Ez[k]));
+        const float lo = -0.5f, hi = (float)c.n[k] - 0.5f;
+        if (r.dq[k] != 0.0f) {
+            const float t1 = (lo - r.qA[k]) / r.dq[k];
+            const float t2 = (hi - r.qA[k]) / r.dq[k];
+            zl = fmaxf(zl, fminf(t1, t2));
+            zh = fminf(zh, fmaxf(t1, t2));
+        } else if (r.qA[k] < lo || r.qA[k] > hi) {
+            return false;
+        }
+    }
+    if (!(zh > zl)) return false;
+    r.z0 = zl;
+    r.z1 = zh;
+    r.h = (zh - zl) / (float)c.S;
+    r.inv_h = (float)c.S / (zh - zl);
+    r.w = r.h * sqrtf(fmaf(us, us, fmaf(vs, vs, 1.0f))) * c.invR;
+    return true;
+}
+
+// First sample index m with z' >= z (samples sit at z0 + (m + 1/2) h).
+__device__ __forceinline__ int sample_bound(const Ray& r, float z, int S)
+{
+    const float t = ceilf(fmaf(z - r.z0, r.inv_h, -0.5f));
+    return (int)fminf(fmaxf(t, 0.0f), (float)S);
+}
+
+__device__ __forceinline__ float slab_edge(const TileRec& t, int k, float chunk)
+{
+    return fmaf((float)k, chunk, t.z_start);
+}
+
+__device__ __forceinline__ float clampf(float v, float lo, float hi)
+{
+    return __builtin_amdgcn_fmed3f(v, lo, hi);
+}
+
+// Trilinear cell of sample position q: clamp to [0, n-1], cell origin
+// i = min(floor(q), n-2) and fraction f = q - i (identical in every kernel).
+struct Cell {
+    float i[3], f[3];
+};
+
+__device__ __forceinline__ Cell cell_of(float qx, float qy, float qz, const float nm1[3])
+{
+    Cell s;
+    const float q[3] = {qx, qy, qz};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float qc = clampf(q[k], 0.0f, nm1[k]);
+        s.i[k] = fminf(floorf(qc), nm1[k] - 1.0f);
+        s.f[k] = qc - s.i[k];
+    }
+    return s;
+}
+
+__device__ __forceinline__ float lerp(float a, float b, float t) { return fmaf(t, b - a, a); }
+
+__device__ __forceinline__ float tri(float c000, float c100, float c010, float c110, float c001,
+                                     float c101, float c011, float c111, const Cell& s)
+{
+    const float x00 = lerp(c000, c100, s.f[0]);
+    const float x10 = lerp(c010, c110, s.f[0]);
+    const float x01 = lerp(c001, c101, s.f[0]);
+    const float x11 = lerp(c011, c111, s.f[0]);
+    return lerp(lerp(x00, x10, s.f[1]), lerp(x01, x11, s.f[1]), s.f[2]);
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ float wave_min(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Block-wide min (is_max = false) or max over kThreads lanes.
+__device__ float block_reduce(float v, bool is_max, float* red)
+{
+    v = is_max ? wave_max(v) : wave_min(v);
+    const int wave = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[wave] = v;
+    __syncthreads();
+    float r = red[0];
+#pragma unroll
+    for (int k = 1; k < kThreads / 64; ++k) r = is_max ? fmaxf(r, red[k]) : fminf(r, red[k]);
+    return r;
+}
+
+// ---------------------------------------------------------------- setup
+// One workgroup per tile: the camera-depth range of the tile's rays, then
+// for each slab the voxel box its samples can touch (with one voxel of
+// margin against rounding).
+__global__ __launch_bounds__(kThreads) void k_setup(CamDev c, TileRec* tiles, BrickRec* bricks)
+{
+    __shared__ float red[kThreads / 64];
+    const int tile = blockIdx.x;
+    float zmin = FLT_MAX, zmax = -FLT_MAX;
+    for (int item = threadIdx.x; item < c.items_per_split; item += kThreads) {
+        int iu, iv;
+        if (!item_pixel(c, tile, item, iu, iv)) continue;
+        for (int rv = 0; rv < c.rv; ++rv)
+            for (int ru = 0; ru < c.ru; ++ru) {
+                Ray r;
+                if (!make_ray(c, iu, iv, ru, rv, r)) continue;
+                zmin = fminf(zmin, r.z0);
+                zmax = fmaxf(zmax, r.z1);
+            }
+    }
+    zmin = block_reduce(zmin, false, red);
+    zmax = block_reduce(zmax, true, red);
+    TileRec t;
+    t.z_start = zmin;
+    t.n_chunks = 0;
+    if (zmax > zmin) {
+        const float span = (zmax - zmin) / c.chunk;
+        t.n_chunks = (int)fminf(fmaxf(ceilf(span), 1.0f), (float)c.max_chunks);
+    }
+    if (threadIdx.x == 0) tiles[tile] = t;
+    const float nm1[3] = {(float)(c.n[0] - 1), (float)(c.n[1] - 1), (float)(c.n[2] - 1)};
+    for (int ch = 0; ch < t.n_chunks; ++ch) {
+        const float za = slab_edge(t, ch, c.chunk);
+        const float zb = (ch == t.n_chunks - 1) ? FLT_MAX : slab_edge(t, ch + 1, c.chunk);
+        float lo[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, hi[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
+        for (int item = threadIdx.x; item < c.items_per_split; item += kThreads) {
+            int iu, iv;
+            if (!item_pixel(c, tile, item, iu, iv)) continue;
+            for (int rv = 0; rv < c.rv; ++rv)
+                for (int ru = 0; ru < c.ru; ++ru) {
+                    Ray r;
+                    if (!make_ray(c, iu, iv, ru, rv, r)) continue;
+                    const float a = fmaxf(za, r.z0), b = fminf(zb, r.z1);
+                    if (a > b) continue;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const float pa = clampf(fmaf(a, r.dq[k], r.qA[k]), 0.0f, nm1[k]);
+                        const float pb = clampf(fmaf(b, r.dq[k], r.qA[k]), 0.0f, nm1[k]);
+                        lo[k] = fminf(lo[k], fminf(pa, pb));
+                        hi[k] = fmaxf(hi[k], fmaxf(pa, pb));
+                    }
+                }
+        }
+        BrickRec br;
+        long long vol = 1;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float l = block_reduce(lo[k], false, red);
+            const float h = block_reduce(hi[k], true, red);
+            int il = 0, ih = 1;
+            if (h >= l) {
+                il = max(0, (int)floorf(l) - 1);
+                ih = min(c.n[k] - 1, (int)floorf(h) + 2);
+                il = min(il, c.n[k] - 2);
+                ih = max(ih, il + 1);
+            }
+            br.lo[k] = il;
+            br.dim[k] = ih - il + 1;
+            vol *= br.dim[k];
+        }
+        br.lds = (vol <= (long long)c.brick_cap) ? 1 : 0;
+        br.base = (float)br.lo[0] + (float)br.dim[0] * ((float)br.lo[1] + (float)br.dim[1] * (float)br.lo[2]);
+        if (threadIdx.x == 0) bricks[(size_t)tile * c.max_chunks + ch] = br;
+    }
+}
+
+// ---------------------------------------------------------------- brick I/O
+__device__ __forceinline__ void brick_coords(int e, int dx, int dy, float inv_dx, float inv_dy,
+                                             int& lx, int& ly, int& lz)
+{
+    // exact for e < 2^20: (e + 1/2)/dx is at least 1/(2 dx) away from an integer
+    const int yz = (int)(((float)e + 0.5f) * inv_dx);
+    lx = e - yz * dx;
+    lz = (int)(((float)yz + 0.5f) * inv_dy);
+    ly = yz - lz * dy;
+}
+
+__device__ __forceinline__ size_t gindex(const int n[3], int x, int y, int z)
+{
+    return (size_t)x + (size_t)n[0] * ((size_t)y + (size_t)n[1] * (size_t)z);
+}
+
+__device__ void stage_brick(const BrickRec& b, const int n[3], const float* __restrict__ x,
+                            float* brick)
+{
+    const int vol = b.dim[0] * b.dim[1] * b.dim[2];
+    const float idx = 1.0f / (float)b.dim[0], idy = 1.0f / (float)b.dim[1];
+    for (int e = threadIdx.x; e < vol; e += kThreads) {
+        int lx, ly, lz;
+        brick_coords(e, b.dim[0], b.dim[1], idx, idy, lx, ly, lz);
+        brick[e] = x[gindex(n, b.lo[0] + lx, b.lo[1] + ly, b.lo[2] + lz)];
+    }
+}
+
+__device__ void zero_brick(const BrickRec& b, double* brick)
+{
+    const int vol = b.dim[0] * b.dim[1] * b.dim[2];
+    for (int e = threadIdx.x; e < vol; e += kThreads) brick[e] = 0.0;
+}
+
+__device__ void flush_brick(const BrickRec& b, const int n[3], double* brick, double* __restrict__ x)
+{
+    const int vol = b.dim[0] * b.dim[1] * b.dim[2];
+    const float idx = 1.0f / (float)b.dim[0], idy = 1.0f / (float)b.dim[1];
+    for (int e = threadIdx.x; e < vol; e += kThreads) {
+        const double v = brick[e];
+        if (v == 0.0) continue;
+        int lx, ly, lz;
+        brick_coords(e, b.dim[0], b.dim[1], idx, idy, lx, ly, lz);
+        unsafeAtomicAdd(&x[gindex(n, b.lo[0] + lx, b.lo[1] + ly, b.lo[2] + lz)], v);
+    }
+}
+
+// ---------------------------------------------------------------- marching
+struct March {
+    float qs[3], st[3];
+};
+
+__device__ __forceinline__ March march_of(const Ray& r)
+{
+    March m;
+    const float zc = fmaf(0.5f, r.h, r.z0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        m.qs[k] = fmaf(zc, r.dq[k], r.qA[k]);
+        m.st[k] = r.h * r.dq[k];
+    }
+    return m;
+}
+
+__device__ __forceinline__ double gather_lds(const March& mr, int m0, int m1, const BrickRec& b,
+                                             const float* brick, const float nm1[3])
+{
+    const float dx = (float)b.dim[0], dxy = (float)(b.dim[0] * b.dim[1]);
+    const int sx = b.dim[0], sxy = b.dim[0] * b.dim[1];
+    const float maxi = (float)(b.dim[0] * b.dim[1] * b.dim[2] - 1 - (1 + sx + sxy));
+    double acc = 0.0;
+    for (int m = m0; m < m1; ++m) {
+        const float fm = (float)m;
+        const Cell s = cell_of(fmaf(fm, mr.st[0], mr.qs[0]), fmaf(fm, mr.st[1], mr.qs[1]),
+                               fmaf(fm, mr.st[2], mr.qs[2]), nm1);
+        const float fi = fmaf(s.i[2], dxy, fmaf(s.i[1], dx, s.i[0])) - b.base;
+        const int i0 = (int)clampf(fi, 0.0f, maxi);
+        const float* p = brick + i0;
+        acc += (double)tri(p[0], p[1], p[sx], p[sx + 1], p[sxy], p[sxy + 1], p[sxy + sx],
+                           p[sxy + sx + 1], s);
+    }
+    return acc;
+}
+
+__device__ __forceinline__ double gather_global(const March& mr, int m0, int m1, const int n[3],
+                                                const float* __restrict__ x, const float nm1[3])
+{
+    const size_t sx = (size_t)n[0], sxy = (size_t)n[0] * n[1];
+    double acc = 0.0;
+    for (int m = m0; m < m1; ++m) {
+        const float fm = (float)m;
+        const Cell s = cell_of(fmaf(fm, mr.st[0], mr.qs[0]), fmaf(fm, mr.st[1], mr.qs[1]),
+                               fmaf(fm, mr.st[2], mr.qs[2]), nm1);
+        const float* p = x + gindex(n, (int)s.i[0], (int)s.i[1], (int)s.i[2]);
+        acc += (double)tri(p[0], p[1], p[sx], p[sx + 1], p[sxy], p[sxy + 1], p[sxy + sx],
+                           p[sxy + sx + 1], s);
+    }
+    return acc;
+}
+
+template <typename Add>
+__device__ __forceinline__ void scatter8(double* p, size_t sx, size_t sxy, const Cell& s, float v,
+                                         Add add)
+{
+    const float gx = 1.0f - s.f[0], gy = 1.0f - s.f[1], gz = 1.0f - s.f[2];
+    const float z0 = v * gz, z1 = v * s.f[2];
+    const float a00 = gy * z0, a10 = s.f[1] * z0, a01 = gy * z1, a11 = s.f[1] * z1;
+    add(p, gx * a00);
+    add(p + 1, s.f[0] * a00);
+    add(p + sx, gx * a10);
+    add(p + sx + 1, s.f[0] * a10);
+    add(p + sxy, gx * a01);
+    add(p + sxy + 1, s.f[0] * a01);
+    add(p + sxy + sx, gx * a11);
+    add(p + sxy + sx + 1, s.f[0] * a11);
+}
+
+__device__ __forceinline__ void scatter_lds(const March& mr, int m0, int m1, const BrickRec& b,
+                                            double* brick, const float nm1[3], float v)
+{
+    const float dx = (float)b.dim[0], dxy = (float)(b.dim[0] * b.dim[1]);
+    const int sx = b.dim[0], sxy = b.dim[0] * b.dim[1];
+    const float maxi = (float)(b.dim[0] * b.dim[1] * b.dim[2] - 1 - (1 + sx + sxy));
+    for (int m = m0; m < m1; ++m) {
+        const float fm = (float)m;
+        const Cell s = cell_of(fmaf(fm, mr.st[0], mr.qs[0]), fmaf(fm, mr.st[1], mr.qs[1]),
+                               fmaf(fm, mr.st[2], mr.qs[2]), nm1);
+        const float fi = fmaf(s.i[2], dxy, fmaf(s.i[1], dx, s.i[0])) - b.base;
+        const int i0 = (int)clampf(fi, 0.0f, maxi);
+        scatter8(brick + i0, (size_t)sx, (size_t)sxy, s, v,
+                 [](double* q, float a) { atomicAdd(q, (double)a); });
+    }
+}
+
+__device__ __forceinline__ void scatter_global(const March& mr, int m0, int m1, const int n[3],
+                                               double* __restrict__ x, const float nm1[3], float v)
+{
+    const size_t sx = (size_t)n[0], sxy = (size_t)n[0] * n[1];
+    for (int m = m0; m < m1; ++m) {
+        const float fm = (float)m;
+        const Cell s = cell_of(fmaf(fm, mr.st[0], mr.qs[0]), fmaf(fm, mr.st[1], mr.qs[1]),
+                               fmaf(fm, mr.st[2], mr.qs[2]), nm1);
+        double* p = x + gindex(n, (int)s.i[0], (int)s.i[1], (int)s.i[2]);
+        scatter8(p, sx, sxy, s, v, [](double* q, float a) { unsafeAtomicAdd(q, (double)a); });
+    }
+}
+
+// ---------------------------------------------------------------- A x, A^T y
+// Dynamic LDS of a march workgroup: the tile's compacted ray list (one
+// uint32 per valid ray: item | aperture sample << 16), one FP64 word per
+// pixel item (forward: the pixel's running sum; adjoint: its y value), then
+// the brick.
+struct Smem {
+    uint32_t* list;
+    double* item;
+    unsigned char* brick;
+};
+
+__device__ __forceinline__ Smem smem_of(unsigned char* base, const CamDev& c)
+{
+    Smem m;
+    m.list = reinterpret_cast<uint32_t*>(base);
+    const int list_bytes = ((c.items_per_split * c.ru * c.rv * 4) + 15) & ~15;
+    const int item_bytes = ((c.items_per_split * 8) + 15) & ~15;
+    m.item = reinterpret_cast<double*>(base + list_bytes);
+    m.brick = base + list_bytes + item_bytes;
+    return m;
+}
+
+// Order-preserving compaction of the tile's valid rays into the LDS list.
+// Pass (k, j) offers ray (j + rot) mod R of item k*kThreads + lane; the
+// valid ones are appended in lane order, so a wave later marches rays that
+// were neighbours in the tile.  Returns the list length (block-uniform).
+template <bool kAdj>
+__device__ int build_ray_list(const CamDev& c, int tile, const Smem& m, int* wsum)
+{
+    const int R = c.ru * c.rv;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rot = c.rotate ? (int)(threadIdx.x % (unsigned)R) : 0;
+    int total = 0;
+    for (int base = 0; base < c.items_per_split; base += kThreads) {
+        const int item = base + threadIdx.x;
+        int iu = 0, iv = 0;
+        const bool have = item_pixel(c, tile, item, iu, iv);
+        const bool lit = have && (!kAdj || m.item[item] != 0.0);
+        for (int j = 0; j < R; ++j) {
+            int rr = j + rot;
+            rr = rr >= R ? rr - R : rr;
+            bool ok = false;
+            if (lit) {
+                const int rv = rr / c.ru, ru = rr - rv * c.ru;
+                Ray r;
+                ok = make_ray(c, iu, iv, ru, rv, r);
+            }
+            const unsigned long long bal = __ballot(ok);
+            const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+            if (lane == 0) wsum[wave] = __popcll(bal);
+            __syncthreads();
+            int off = total, all = 0;
+#pragma unroll
+            for (int w = 0; w < kThreads / 64; ++w) {
+                off += (w < wave) ? wsum[w] : 0;
+                all += wsum[w];
+            }
+            if (ok) m.list[off + pre] = (uint32_t)item | ((uint32_t)rr << 16);
+            total += all;
+            __syncthreads();
+        }
+    }
+    return total;
+}
+
+template <bool kAdj>
+__global__ __launch_bounds__(kThreads) void k_march(CamDev c, const float* __restrict__ in,
+                                                    float* __restrict__ yout,
+                                                    double* __restrict__ xacc)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int wsum[kThreads / 64];
+    const Smem m = smem_of(smem, c);
+    const int tile = blockIdx.x;
+    const TileRec t = c.tiles[tile];
+    const float nm1[3] = {(float)(c.n[0] - 1), (float)(c.n[1] - 1), (float)(c.n[2] - 1)};
+
+    // per-item words: forward sums start at 0, the adjoint reads y once
+    for (int item = threadIdx.x; item < c.items_per_split; item += kThreads) {
+        double v = 0.0;
+        if (kAdj) {
+            int iu, iv;
+            if (item_pixel(c, tile, item, iu, iv)) v = (double)in[c.y_off + (size_t)iv * c.nu + iu];
+        }
+        m.item[item] = v;
+    }
+    __syncthreads();
+    const int nrays = t.n_chunks > 0 ? build_ray_list<kAdj>(c, tile, m, wsum) : 0;
+
+    for (int ch = 0; ch < t.n_chunks && nrays > 0; ++ch) {
+        const BrickRec b = c.bricks[(size_t)tile * c.max_chunks + ch];
+        const float za = slab_edge(t, ch, c.chunk);
+        const float zb = slab_edge(t, ch + 1, c.chunk);
+        const bool last = ch == t.n_chunks - 1;
+        if (b.lds) {
+            __syncthreads();
+            if (kAdj)
+                zero_brick(b, reinterpret_cast<double*>(m.brick));
+            else
+                stage_brick(b, c.n, in, reinterpret_cast<float*>(m.brick));
+            __syncthreads();
+        }
+        for (int e = threadIdx.x; e < nrays; e += kThreads) {
+            const uint32_t id = m.list[e];
+            const int item = (int)(id & 0xffffu), rr = (int)(id >> 16);
+            int iu, iv;
+            item_pixel(c, tile, item, iu, iv);
+            const int rv = rr / c.ru, ru = rr - rv * c.ru;
+            Ray r;
+            make_ray(c, iu, iv, ru, rv, r);
+            const int m0 = sample_bound(r, za, c.S);
+            const int m1 = last ? c.S : sample_bound(r, zb, c.S);
+            if (m0 >= m1) continue;
+            const March mr = march_of(r);
+            if (!kAdj) {
+                const double s = b.lds ? gather_lds(mr, m0, m1, b, reinterpret_cast<const float*>(m.brick), nm1)
+                                       : gather_global(mr, m0, m1, c.n, in, nm1);
+                atomicAdd(&m.item[item], s * (double)r.w);
+            } else {
+                const float v = (float)m.item[item] * r.w;
+                if (b.lds)
+                    scatter_lds(mr, m0, m1, b, reinterpret_cast<double*>(m.brick), nm1, v);
+                else
+                    scatter_global(mr, m0, m1, c.n, xacc, nm1, v);
+            }
+        }
+        if (kAdj && b.lds) {
+            __syncthreads();
+            flush_brick(b, c.n, reinterpret_cast<double*>(m.brick), xacc);
+        }
+    }
+    if (!kAdj) {
+        __syncthreads();
+        for (int item = threadIdx.x; item < c.items_per_split; item += kThreads) {
+            int iu, iv;
+            if (item_pixel(c, tile, item, iu, iv))
+                yout[c.y_off + (size_t)iv * c.nu + iu] = (float)m.item[item];
+        }
+    }
+}
+
+__global__ void k_fill(float* p, uint64_t n, float v)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Valid-ray count: one thread per pixel, block sum, one atomic per block.
+__global__ __launch_bounds__(kThreads) void k_count(CamDev c, unsigned long long* counter)
+{
+    __shared__ unsigned int red[kThreads / 64];
+    unsigned int cnt = 0;
+    const long long npix = (long long)c.nu * c.nv;
+    for (long long p = (long long)blockIdx.x * kThreads + threadIdx.x; p < npix;
+         p += (long long)gridDim.x * kThreads) {
+        const int iu = (int)(p % c.nu), iv = (int)(p / c.nu);
+        for (int rv = 0; rv < c.rv; ++rv)
+            for (int ru = 0; ru < c.ru; ++ru) {
+                Ray r;
+                cnt += make_ray(c, iu, iv, ru, rv, r) ? 1u : 0u;
+            }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int k = 0; k < kThreads / 64; ++k) t += red[k];
+        atomicAdd(counter, t);
+    }
+}
+
+__global__ void k_fill64(double* p, uint64_t n)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, uint64_t n)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        b[i] = (float)a[i];
+}
+
+unsigned grid_for(uint64_t n)
+{
+    uint64_t blocks = (n + 255) / 256;
+    return (unsigned)(blocks > 8192 ? 8192 : (blocks ? blocks : 1));
+}
+
+
+}  // namespace
+
+hipError_t launch_fill(float* p, uint64_t n, float v, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_count(const CamDev& c, unsigned long long* counter, hipStream_t s)
+{
+    const long long npix = (long long)c.nu * c.nv;
+    long long blocks = (npix + kThreads - 1) / kThreads;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_count, dim3((unsigned)blocks), dim3(kThreads), 0, s, c, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup(const CamDev& c, int dir, hipStream_t s)
+{
+    (void)dir;
+    hipLaunchKernelGGL(k_setup, dim3(c.n_tiles), dim3(kThreads), 0, s, c,
+                       const_cast<TileRec*>(c.tiles), const_cast<BrickRec*>(c.bricks));
+    return hipGetLastError();
+}
+
+size_t march_lds_bytes(const CamDev& c, int dir)
+{
+    const size_t list_bytes = ((size_t)c.items_per_split * c.ru * c.rv * 4 + 15) & ~size_t(15);
+    const size_t item_bytes = ((size_t)c.items_per_split * 8 + 15) & ~size_t(15);
+    const size_t brick_bytes = (size_t)c.brick_cap * (dir == LTM_ADJOINT ? 8 : 4);
+    return list_bytes + item_bytes + brick_bytes;
+}
+
+hipError_t launch_project(const CamDev& c, const float* x, float* y, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_march<false>, dim3(c.n_tiles), dim3(kThreads),
+                       march_lds_bytes(c, LTM_FORWARD), s, c, x, y, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill64(double* p, uint64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill64, dim3(grid_for(n)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_f32(const double* a, float* b, uint64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(256), 0, s, a, b, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_backproject(const CamDev& c, const float* y, double* x, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_march<true>, dim3(c.n_tiles), dim3(kThreads),
+                       march_lds_bytes(c, LTM_ADJOINT), s, c, y, nullptr, x);
+    return hipGetLastError();
+}
+
+}  // namespace ltm
