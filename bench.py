@@ -72,48 +72,22 @@ def cpu_baseline(g, cams, x, valid_fraction, target_s=12.0):
                        f"fraction {valid_fraction:.4f}; {t_fwd:.1f} s + {t_adj:.1f} s")}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU path is a design, not a build", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
+def time_pair(plan, x, y, xt, steps, warmup):
+    """Event-timed steps of (project, backproject) on torch's current stream."""
     import torch
 
-    from paper_1812_03358_amd import ltm, workloads as W
-
-    cfg = W.config_plenoptic()
-    g, cams = cfg["grid"], cfg["cameras"]
-    x_host = cfg["volume"]()
-    plan = ltm.Plan(g, cams)
-    x = torch.from_numpy(x_host.reshape(-1)).cuda()
-    y = plan.project(x)
-    xt = torch.empty_like(x)
-    torch.cuda.synchronize()
-    valid = plan.valid_samples()
-    nominal = sum(ltm_nominal(c) for c in cams)
-
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         plan.project(x, y)
         plan.backproject(y, xt)
     torch.cuda.synchronize()
-
     stream = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
-           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+           torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_wall = time.perf_counter()
     start.record(stream)
-    for k in range(args.steps):
+    for k in range(steps):
         ev[k][0].record(stream)
         plan.project(x, y)
         ev[k][1].record(stream)
@@ -123,22 +97,26 @@ def main():
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
     total_ms = start.elapsed_time(stop)
-    fwd_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
-    adj_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / args.steps
-    ms_step = total_ms / args.steps
-    value = 2.0 * valid / (ms_step * 1e-3) / 1e9
+    fwd_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
+    adj_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
+    return total_ms / steps, fwd_ms, adj_ms, t_wall
 
+
+def roofline_of(valid, fwd_ms, adj_ms):
     dominant = "backproject" if adj_ms >= fwd_ms else "project"
     dom_ms = max(adj_ms, fwd_ms)
     achieved = FLOP_PER_SAMPLE[dominant] * valid / (dom_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_TFLOPS, 2),
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": None, "kernel": "k_backproject" if dominant == "backproject" else "k_project",
-                "ms_per_launch": round(dom_ms, 4)}
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_TFLOPS, 2),
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+            "kernel": "k_march<true> (adjoint)" if dominant == "backproject" else "k_march<false> (forward)",
+            "ms_per_launch": round(dom_ms, 4)}
     gather = {d: round(valid / (ms * 1e-3) * GATHER_BYTES_PER_SAMPLE / 1e9 / HBM_PEAK_GBS, 4)
               for d, ms in (("project", fwd_ms), ("backproject", adj_ms))}
+    return roof, gather
 
-    out = {
+
+def base_record(args, value, ms_step, workload, extra_config):
+    return {
         "metric": "ray-samples/s for A x + A^T y (% HBM roofline)",
         "value": round(value, 3),
         "unit": "Gsamples/s",
@@ -151,19 +129,194 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "plenoptic_128: 128^3 flame volume (1.25 mm voxels), 1 plenoptic "
-                               "camera 1024^2 px behind 64^2 lenslets, 2x2 rays/pixel, 256 "
-                               "samples/ray; one A x + one A^T y per step",
-                   "valid_samples_per_direction": valid, "nominal_samples_per_direction": nominal,
-                   "parallelism": "single GPU"},
-        "roofline": roofline,
-        "gather_equivalent_hbm_frac": gather,
-        "ms_project": round(fwd_ms, 4),
-        "ms_backproject": round(adj_ms, 4),
-        "wall_s_timed": round(t_wall, 3),
+        "config": dict({"workload": workload, "parallelism": "single GPU"}, **extra_config),
     }
+
+
+def copy_probe():
+    """A plain 256 MiB device copy, so counter runs can scale their byte
+    counts against a kernel of known traffic."""
+    import torch
+
+    src = torch.ones(64 << 20, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+
+
+def run_single(args, cfg, workload):
+    import torch
+
+    from paper_1812_03358_amd import ltm
+
+    g, cams = cfg["grid"], cfg["cameras"]
+    x_host = cfg["volume"]()
+    plan = ltm.Plan(g, cams)
+    x = torch.from_numpy(x_host.reshape(-1)).cuda()
+    y = plan.project(x)
+    xt = torch.empty_like(x)
+    torch.cuda.synchronize()
+    valid = plan.valid_samples()
+    nominal = sum(ltm_nominal(c) for c in cams)
+    ms_step, fwd_ms, adj_ms, t_wall = time_pair(plan, x, y, xt, args.steps, args.warmup)
+    value = 2.0 * valid / (ms_step * 1e-3) / 1e9
+    out = base_record(args, value, ms_step, workload,
+                      {"valid_samples_per_direction": valid, "nominal_samples_per_direction": nominal})
+    out["roofline"], out["gather_equivalent_hbm_frac"] = roofline_of(valid, fwd_ms, adj_ms)
+    out["ms_project"] = round(fwd_ms, 4)
+    out["ms_backproject"] = round(adj_ms, 4)
+    out["gsamples_per_s_project"] = round(valid / (fwd_ms * 1e-3) / 1e9, 2)
+    out["gsamples_per_s_backproject"] = round(valid / (adj_ms * 1e-3) / 1e9, 2)
+    out["wall_s_timed"] = round(t_wall, 3)
+    if args.copy_probe:
+        copy_probe()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, cams, x_host, valid / nominal, args.cpu_seconds)
+    return out
+
+
+def run_batched(args):
+    """48 frames x 4 plenoptic cameras: autotuned tilings, one graph replay
+    of the persistent A sweep then A^T sweep per step."""
+    import numpy as np
+    import torch
+
+    from paper_1812_03358_amd import autotune, ltm, workloads as W
+
+    frames = W.config_batched()
+    cache = args.autotune_cache or os.path.join("/tmp", "ltm_autotune_%d.json" % os.getpid())
+    plans, xs, ys, xts = [], [], [], []
+    tuned = {}
+    t0 = time.perf_counter()
+    for f in frames:
+        n = f["grid"]["nx"]
+        p = ltm.Plan(f["grid"], f["cameras"])
+        x = torch.from_numpy(W.flame(n, f["volume_seed"]).reshape(-1)).cuda()
+        y = torch.empty(p.n_meas, device="cuda")
+        if n not in tuned and not args.no_autotune:
+            p.project(x, y)
+            tuned[n] = autotune.autotune_plan(p, x, y, reps=2, cache=cache)
+        elif not args.no_autotune:
+            for ci in range(len(f["cameras"])):
+                for d in (0, 1):
+                    autotune.autotune(p, ci, d, x, y, cache=cache)
+        plans.append(p)
+        xs.append(x)
+        ys.append(y)
+        xts.append(torch.empty_like(x))
+    t_setup = time.perf_counter() - t0
+    valid = sum(p.valid_samples() for p in plans)
+    nominal = sum(ltm_nominal(c) for f in frames for c in f["cameras"])
+    batch = ltm.Batch(plans, xs, ys, xts)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        batch.sweep(s)
+        s.synchronize()
+        batch.capture(s)
+        for _ in range(args.warmup):
+            batch.replay(s)
+        s.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        for _ in range(args.steps):
+            batch.replay(s)
+        b.record(s)
+        s.synchronize()
+    ms = a.elapsed_time(b) / args.steps
+    value = 2.0 * valid / (ms * 1e-3) / 1e9
+    out = base_record(args, value, ms, "batched_48: 48 flame frames (12 each of 96/128/160/192^3, "
+                      "160 mm cube) x 4 plenoptic cameras at 0/30/60/90 deg, 1024^2 px, 64^2 "
+                      "lenslets, 2x2 rays, S = 2n; one hipGraph replay of the persistent A sweep "
+                      "and A^T sweep per step",
+                      {"valid_samples_per_direction": valid, "nominal_samples_per_direction": nominal})
+    out["setup_s_incl_autotune"] = round(t_setup, 2)
+    out["autotune"] = {str(n): [{"ms": round(r["ms"], 4), "default_ms": round(r["default_ms"], 4)}
+                                for r in res] for n, res in tuned.items()}
+    return out
+
+
+def run_recon(args):
+    """Reconstruction on the 128^3 plenoptic workload: FISTA with the
+    hyperbola potential on Poisson data, per-iteration time and final rho."""
+    import numpy as np
+    import torch
+
+    from paper_1812_03358_amd import ltm, workloads as W
+
+    cfg = W.config_plenoptic()
+    g, cams = cfg["grid"], cfg["cameras"]
+    plan = ltm.Plan(g, cams)
+    xt = torch.from_numpy(cfg["volume"]().reshape(-1)).cuda()
+    y_clean = plan.project(xt).cpu().numpy()
+    y = torch.from_numpy(W.poisson_noise(y_clean, seed=cfg["noise_seed"])).cuda()
+    # majorizer scale for the edge-preserving weight: 36 beta = 1% of median D
+    probe = ltm.Solver(plan, y, momentum=True)
+    d = plan.backproject(plan.project(torch.ones(plan.n_voxels, device="cuda")))
+    dpos = d[d > 0]
+    beta = 0.01 * float(dpos.median()) / 36.0
+    del probe
+    solver = ltm.Solver(plan, y, beta=beta, psi_kind=ltm.PSI_HYPERBOLA, delta=0.02, momentum=True)
+    solver.step(2)
+    torch.cuda.synchronize()
+    solver.reset()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    solver.step(args.iters)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    rho, it = solver.residual()
+    x = solver.x()
+    err = float(torch.linalg.norm(x - xt) / torch.linalg.norm(xt))
+    out = base_record(args, 1000.0 * args.iters / ms, ms / args.iters,
+                      f"recon_plenoptic_128: FISTA, hyperbola potential (delta 0.02), "
+                      f"{args.iters} iterations, Poisson data at peak 1000", {"beta": beta})
+    out["metric"] = "reconstruction iterations/s"
+    out["unit"] = "iterations/s"
+    out["final_rho"] = rho
+    out["iterations"] = it
+    out["rel_error_to_truth"] = err
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="plenoptic_128",
+                    choices=["plenoptic_128", "thin_lens_32", "differentiable_256", "batched_48",
+                             "recon_plenoptic_128"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--autotune-cache", default=None)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--iters", type=int, default=100)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU path is a design, not a build", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1812_03358_amd import workloads as W
+
+    if args.workload == "plenoptic_128":
+        out = run_single(args, W.config_plenoptic(), "plenoptic_128: 128^3 flame volume (1.25 mm "
+                         "voxels), 1 plenoptic camera 1024^2 px behind 64^2 lenslets, 2x2 rays/pixel, "
+                         "256 samples/ray; one A x + one A^T y per step")
+    elif args.workload == "thin_lens_32":
+        out = run_single(args, W.config_thin_lens(), "thin_lens_32: 32^3 blobs, single-lens camera "
+                         "64^2, 1 ray/pixel, 64 samples/ray; one A x + one A^T y per step")
+    elif args.workload == "differentiable_256":
+        out = run_single(args, W.config_differentiable(), "differentiable_256: 256^3 flame, 4 "
+                         "plenoptic cameras 2048^2 (128^2 lenslets) at 0/30/60/90 deg, 2x1 rays, "
+                         "512 samples; one A x + one A^T y per step")
+    elif args.workload == "batched_48":
+        out = run_batched(args)
+    else:
+        out = run_recon(args)
     print(json.dumps(out), flush=True)
 
 

@@ -211,10 +211,56 @@ ltm_status ltm_solver_residual(ltm_solver* solver, double* rho, uint32_t* iterat
  * projection).  Synchronizes the stream. */
 ltm_status ltm_solver_residual_x(ltm_solver* solver, double* rho, void* stream);
 
+/* Checkpoint: copy the iterate x and the extrapolated point z (N floats
+ * each, device) and return FISTA's t, the iteration count and the n_cam
+ * current gains (host array, or NULL).  Synchronizes the stream. */
+ltm_status ltm_solver_save(const ltm_solver* solver, float* x, float* z, double* t,
+                           uint32_t* iterations, double* gains, void* stream);
+
+/* Resume from a checkpoint written by ltm_solver_save (t >= 1).  Gains may be
+ * NULL to keep the current ones.  Synchronizes the stream. */
+ltm_status ltm_solver_load(ltm_solver* solver, const float* x, const float* z, double t,
+                           uint32_t iterations, const double* gains, void* stream);
+
 /* Gradient of R at z added into g:  g += beta sum_{l in N_j} psi'(z_j - z_l).
  * z, g: N floats on the device. */
 ltm_status ltm_reg_grad_add(const ltm_grid* grid, uint32_t psi_kind, double beta, double delta,
                             const float* z, float* g, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Batched sweeps.  Several bound plans -- for instance the time frames of a
+ * sequence, each with its own grid size and cameras -- are projected by ONE
+ * persistent launch and backprojected by another.  Each workgroup takes
+ * (plan, camera, tile) items from a device counter, costliest first, so
+ * uneven frames share the GPU without a launch per camera.  The sweep
+ * allocates nothing, never synchronizes with the host and records no memset,
+ * so it can be captured in a hipGraph (ltm_batch_graph_capture) and
+ * replayed.  The plans' tilings and workspaces must not change while the
+ * batch is used. */
+typedef struct ltm_batch ltm_batch;
+
+ltm_status ltm_batch_create(ltm_plan* const* plans, uint32_t n_plans, ltm_batch** out);
+void ltm_batch_destroy(ltm_batch* batch);
+ltm_status ltm_batch_workspace_bytes(const ltm_batch* batch, uint64_t* bytes);
+
+/* Bind a device workspace and, per plan k, its buffers: x_in[k] (N_k floats,
+ * read by the forward), y[k] (M_k floats, written by the forward and read by
+ * the adjoint) and x_out[k] (N_k floats, written by the adjoint).  The three
+ * arguments are host arrays of n_plans device pointers.  Synchronizes. */
+ltm_status ltm_batch_bind(ltm_batch* batch, void* ws, uint64_t bytes, const float* const* x_in,
+                          float* const* y, float* const* x_out, void* stream);
+
+/* y_k = A_k x_in_k for every plan. */
+ltm_status ltm_batch_project(ltm_batch* batch, void* stream);
+/* x_out_k = A_k^T y_k for every plan. */
+ltm_status ltm_batch_backproject(ltm_batch* batch, void* stream);
+/* Both, forward first. */
+ltm_status ltm_batch_sweep(ltm_batch* batch, void* stream);
+
+/* Capture one ltm_batch_sweep on `stream` (not the null stream) into a
+ * graph owned by the batch; replay it with ltm_batch_graph_launch. */
+ltm_status ltm_batch_graph_capture(ltm_batch* batch, void* stream);
+ltm_status ltm_batch_graph_launch(ltm_batch* batch, void* stream);
 
 #ifdef __cplusplus
 }

@@ -67,6 +67,17 @@ struct CamDev {
     uint64_t y_off;
 };
 
+// One (plan, camera) of a batch: its constants and the buffers it reads and
+// writes (x: the plan's input volume, y: its image block, xacc: the plan's
+// FP64 adjoint accumulator).
+struct BatchCam {
+    CamDev cam;
+    const float* x;
+    float* y;
+    double* xacc;
+};
+constexpr int kTileBits = 20;   // work item = (batch camera << 20) | tile
+
 struct CamHost {
     ltm_camera desc;
     ltm_tiling tiling[2];
@@ -107,6 +118,9 @@ hipError_t launch_to_f32(const double* a, float* b, uint64_t n, hipStream_t s);
 hipError_t launch_fill(float* p, uint64_t n, float v, hipStream_t s);
 hipError_t launch_count(const CamDev& c, unsigned long long* counter, hipStream_t s);
 size_t march_lds_bytes(const CamDev& c, int dir);
+hipError_t launch_batch(const BatchCam* cams, const uint32_t* items, uint32_t n_items,
+                        unsigned int* counter, int dir, int blocks, size_t lds, hipStream_t s);
+int batch_blocks_per_cu(int dir, size_t lds);
 
 // the camera's constants with the tables of one direction bound
 CamDev bound_dev(const ltm_plan* p, const CamHost& c, int dir);

@@ -469,15 +469,15 @@ __device__ int build_ray_list(const CamDev& c, int tile, const Smem& m, int* wsu
     return total;
 }
 
+// One tile of one camera: compact its rays, march them slab by slab, and
+// write the tile's pixels (forward) or flush its bricks (adjoint).  Shared by
+// the one-camera launch and the persistent batch kernel.
 template <bool kAdj>
-__global__ __launch_bounds__(kThreads) void k_march(CamDev c, const float* __restrict__ in,
-                                                    float* __restrict__ yout,
-                                                    double* __restrict__ xacc)
+__device__ void march_tile(const CamDev& c, int tile, const float* __restrict__ in,
+                           float* __restrict__ yout, double* __restrict__ xacc,
+                           unsigned char* smem, int* wsum)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int wsum[kThreads / 64];
     const Smem m = smem_of(smem, c);
-    const int tile = blockIdx.x;
     const TileRec t = c.tiles[tile];
     const float nm1[3] = {(float)(c.n[0] - 1), (float)(c.n[1] - 1), (float)(c.n[2] - 1)};
 
@@ -543,6 +543,52 @@ __global__ __launch_bounds__(kThreads) void k_march(CamDev c, const float* __res
                 yout[c.y_off + (size_t)iv * c.nu + iu] = (float)m.item[item];
         }
     }
+    __syncthreads();   // the caller may reuse the LDS for the next tile
+}
+
+template <bool kAdj>
+__global__ __launch_bounds__(kThreads) void k_march(CamDev c, const float* __restrict__ in,
+                                                    float* __restrict__ yout,
+                                                    double* __restrict__ xacc)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int wsum[kThreads / 64];
+    march_tile<kAdj>(c, blockIdx.x, in, yout, xacc, smem, wsum);
+}
+
+// Persistent sweep over many (plan, camera, tile) items: each workgroup
+// takes the next item from a global counter until the list is exhausted
+// (every workgroup reaches the exit once the counter passes n_items).
+// Items are ordered by decreasing estimated cost.
+template <bool kAdj>
+__global__ __launch_bounds__(kThreads) void k_batch(const BatchCam* __restrict__ cams,
+                                                    const uint32_t* __restrict__ items,
+                                                    uint32_t n_items,
+                                                    unsigned int* __restrict__ counter)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int wsum[kThreads / 64];
+    __shared__ uint32_t next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t k = next;
+        __syncthreads();
+        if (k >= n_items) break;
+        const uint32_t it = items[k];
+        const int pc = __builtin_amdgcn_readfirstlane((int)(it >> kTileBits));
+        const int tile = __builtin_amdgcn_readfirstlane((int)(it & ((1u << kTileBits) - 1u)));
+        const BatchCam& bc = cams[pc];
+        if (kAdj)
+            march_tile<true>(bc.cam, tile, bc.y, nullptr, bc.xacc, smem, wsum);
+        else
+            march_tile<false>(bc.cam, tile, bc.x, bc.y, nullptr, smem, wsum);
+    }
+}
+
+__global__ void k_zero_u32(unsigned int* p, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
 }
 
 __global__ void k_fill(float* p, uint64_t n, float v)
@@ -640,6 +686,28 @@ hipError_t launch_project(const CamDev& c, const float* x, float* y, hipStream_t
     hipLaunchKernelGGL(k_march<false>, dim3(c.n_tiles), dim3(kThreads),
                        march_lds_bytes(c, LTM_FORWARD), s, c, x, y, nullptr);
     return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchCam* cams, const uint32_t* items, uint32_t n_items,
+                        unsigned int* counter, int dir, int blocks, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, counter, 1);
+    if (dir == LTM_ADJOINT)
+        hipLaunchKernelGGL(k_batch<true>, dim3(blocks), dim3(kThreads), lds, s, cams, items, n_items,
+                           counter);
+    else
+        hipLaunchKernelGGL(k_batch<false>, dim3(blocks), dim3(kThreads), lds, s, cams, items, n_items,
+                           counter);
+    return hipGetLastError();
+}
+
+int batch_blocks_per_cu(int dir, size_t lds)
+{
+    int n = 0;
+    hipError_t e = dir == LTM_ADJOINT
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<true>, kThreads, lds)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<false>, kThreads, lds);
+    return (e == hipSuccess && n > 0) ? n : 1;
 }
 
 hipError_t launch_fill64(double* p, uint64_t n, hipStream_t s)

@@ -94,6 +94,19 @@ _SIGS = {
     "ltm_solver_get_x": (ctypes.c_int, [_VP, _VP, _VP]),
     "ltm_solver_residual": (ctypes.c_int, [_VP, ctypes.POINTER(_D), ctypes.POINTER(_U32), _VP]),
     "ltm_solver_residual_x": (ctypes.c_int, [_VP, ctypes.POINTER(_D), _VP]),
+    "ltm_solver_save": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_U32),
+                                       _VP, _VP]),
+    "ltm_solver_load": (ctypes.c_int, [_VP, _VP, _VP, _D, _U32, _VP, _VP]),
+    "ltm_batch_create": (ctypes.c_int, [ctypes.POINTER(_VP), _U32, ctypes.POINTER(_VP)]),
+    "ltm_batch_destroy": (None, [_VP]),
+    "ltm_batch_workspace_bytes": (ctypes.c_int, [_VP, ctypes.POINTER(_U64)]),
+    "ltm_batch_bind": (ctypes.c_int, [_VP, _VP, _U64, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
+                                      ctypes.POINTER(_VP), _VP]),
+    "ltm_batch_project": (ctypes.c_int, [_VP, _VP]),
+    "ltm_batch_backproject": (ctypes.c_int, [_VP, _VP]),
+    "ltm_batch_sweep": (ctypes.c_int, [_VP, _VP]),
+    "ltm_batch_graph_capture": (ctypes.c_int, [_VP, _VP]),
+    "ltm_batch_graph_launch": (ctypes.c_int, [_VP, _VP]),
     "ltm_reg_grad_add": (ctypes.c_int, [ctypes.POINTER(Grid), _U32, _D, _D, _VP, _VP, _VP]),
 }
 
@@ -288,10 +301,71 @@ class Solver:
                                          _stream(stream)))
         return rho.value, it.value
 
+    def save(self, stream=None):
+        """Checkpoint: (x, z, t, iterations, gains)."""
+        n = self.plan.n_voxels
+        x = torch.empty(n, dtype=torch.float32, device=self.y.device)
+        z = torch.empty_like(x)
+        t, it = ctypes.c_double(), ctypes.c_uint32()
+        gains = (ctypes.c_double * len(self.plan.cameras))()
+        _check(lib().ltm_solver_save(self._h, _ptr(x), _ptr(z), ctypes.byref(t), ctypes.byref(it),
+                                     ctypes.cast(gains, ctypes.c_void_p), _stream(stream)))
+        return x, z, t.value, it.value, list(gains)
+
+    def load(self, state, stream=None):
+        x, z, t, it, gains = state
+        g = (ctypes.c_double * len(gains))(*gains)
+        _check(lib().ltm_solver_load(self._h, _ptr(x, numel=self.plan.n_voxels),
+                                     _ptr(z, numel=self.plan.n_voxels), float(t), int(it),
+                                     ctypes.cast(g, ctypes.c_void_p), _stream(stream)))
+
     def residual_x(self, stream=None) -> float:
         rho = ctypes.c_double()
         _check(lib().ltm_solver_residual_x(self._h, ctypes.byref(rho), _stream(stream)))
         return rho.value
+
+
+class Batch:
+    """One persistent sweep over several plans (see ltm_batch_* in ltm.h).
+
+    x_in, y, x_out: lists of GPU tensors, one per plan."""
+
+    def __init__(self, plans, x_in, y, x_out, stream=None):
+        self.plans = list(plans)
+        self.buffers = (list(x_in), list(y), list(x_out))
+        arr = (_VP * len(self.plans))(*[p.handle for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(lib().ltm_batch_create(arr, len(self.plans), ctypes.byref(h)))
+        self._h = h
+        b = ctypes.c_uint64()
+        _check(lib().ltm_batch_workspace_bytes(h, ctypes.byref(b)))
+        self.workspace = torch.empty(b.value, dtype=torch.uint8, device=y[0].device)
+        for p, a, bb, c in zip(self.plans, x_in, y, x_out):
+            _ptr(a, numel=p.n_voxels), _ptr(bb, numel=p.n_meas), _ptr(c, numel=p.n_voxels)
+        mk = lambda ts: (_VP * len(ts))(*[t.data_ptr() for t in ts])
+        _check(lib().ltm_batch_bind(h, ctypes.c_void_p(self.workspace.data_ptr()), b.value,
+                                    mk(x_in), mk(y), mk(x_out), _stream(stream)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.ltm_batch_destroy(h)
+            self._h = None
+
+    def project(self, stream=None):
+        _check(lib().ltm_batch_project(self._h, _stream(stream)))
+
+    def backproject(self, stream=None):
+        _check(lib().ltm_batch_backproject(self._h, _stream(stream)))
+
+    def sweep(self, stream=None):
+        _check(lib().ltm_batch_sweep(self._h, _stream(stream)))
+
+    def capture(self, stream):
+        _check(lib().ltm_batch_graph_capture(self._h, _stream(stream)))
+
+    def replay(self, stream=None):
+        _check(lib().ltm_batch_graph_launch(self._h, _stream(stream)))
 
 
 def reg_grad_add(grid: dict, z: torch.Tensor, g: torch.Tensor, beta: float, psi_kind: int,

@@ -1,0 +1,114 @@
+"""The C ABI on the host: the library loads without a GPU, exports every
+function include/ltm.h declares, and validates descriptors before any
+launch (error codes and messages)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1812_03358_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1812_03358_amd import ltm
+    return ltm
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "ltm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ltm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_function_is_exported(L):
+    lib = L.lib()
+    names = header_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding knows every one of them
+    assert set(names) <= set(L.declared_symbols())
+
+
+def test_abi_version(L):
+    assert L.lib().ltm_abi_version() == 1
+
+
+def _create(L, g, cams):
+    gg = L.make_grid(g)
+    cc = L.make_cameras(cams)
+    h = ctypes.c_void_p()
+    st = L.lib().ltm_plan_create(ctypes.byref(gg), cc, len(cams), ctypes.byref(h))
+    msg = L.lib().ltm_last_error().decode()
+    if st == 0:
+        L.lib().ltm_plan_destroy(h)
+    return st, msg
+
+
+def test_valid_plan_and_sizes(L):
+    g = W.grid(128, 1.25)
+    cams = [W.plenoptic_camera(), W.single_lens_camera(64, (2, 2), 9, phi_deg=30.0)]
+    gg, cc, h = L.make_grid(g), L.make_cameras(cams), ctypes.c_void_p()
+    assert L.lib().ltm_plan_create(ctypes.byref(gg), cc, 2, ctypes.byref(h)) == 0
+    nv, nm = ctypes.c_uint64(), ctypes.c_uint64()
+    assert L.lib().ltm_plan_sizes(h, ctypes.byref(nv), ctypes.byref(nm)) == 0
+    assert nv.value == 128 ** 3 and nm.value == 1024 * 1024 + 64 * 64
+    b = ctypes.c_uint64()
+    assert L.lib().ltm_plan_workspace_bytes(h, ctypes.byref(b)) == 0
+    assert b.value >= 8 * 128 ** 3                      # FP64 adjoint accumulator
+    # unbound plan refuses to launch
+    st = L.lib().ltm_project(h, ctypes.c_void_p(8), ctypes.c_void_p(8), None)
+    assert st == L.LTM_ERR_WORKSPACE
+    t = L.Tiling()
+    assert L.lib().ltm_plan_get_tiling(h, 1, 0, ctypes.byref(t)) == 0
+    t.order = 7
+    assert L.lib().ltm_plan_set_tiling(h, 1, 0, ctypes.byref(t)) == L.LTM_ERR_INVALID
+    t.order = 1
+    t.splits = 1
+    t.tile_u = t.tile_v = 16                             # 65536 pixels in one workgroup
+    assert L.lib().ltm_plan_set_tiling(h, 1, 0, ctypes.byref(t)) == L.LTM_ERR_INVALID
+    L.lib().ltm_plan_destroy(h)
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda g, c: g.update(nx=1), "at least 2"),
+    (lambda g, c: g.update(pitch=0.0), "pitch"),
+    (lambda g, c: c.update(det_nu=1001), "multiple"),
+    (lambda g, c: c.update(samples=0), "samples"),
+    (lambda g, c: c.update(rays_u=9, rays_v=9), "rays"),
+    (lambda g, c: c.update(f_mla=-3.0), "positive"),
+    (lambda g, c: c.update(axes=[1, 0, 0, 0, 1, 0, 0, 0, -1]), "right-handed"),
+    (lambda g, c: c.update(axes=[1, 0, 0, 0, 2, 0, 0, 0, 1]), "orthonormal"),
+    (lambda g, c: c.update(kind=7), "kind"),
+    (lambda g, c: c.update(det_nu=0), "empty"),
+])
+def test_invalid_descriptors_rejected(L, mutate, needle):
+    g = W.grid(16, 1.0)
+    c = W.plenoptic_camera(64, 4, (2, 2), 8)
+    mutate(g, c)
+    st, msg = _create(L, g, [c])
+    assert st == L.LTM_ERR_INVALID
+    assert needle in msg
+
+
+def test_solver_requires_bound_plan(L):
+    g = W.grid(8, 1.0)
+    gg, cc, h = L.make_grid(g), L.make_cameras([W.single_lens_camera(8, (1, 1), 4)]), ctypes.c_void_p()
+    assert L.lib().ltm_plan_create(ctypes.byref(gg), cc, 1, ctypes.byref(h)) == 0
+    prm = L.SolverParams(1, 0, 0, 0, 0.0, 1.0, 0.0, 36.0)
+    out = ctypes.c_void_p()
+    st = L.lib().ltm_solver_create(h, ctypes.byref(prm), ctypes.c_void_p(256), None,
+                                   ctypes.c_void_p(256), 1 << 20, None, ctypes.byref(out))
+    assert st == L.LTM_ERR_WORKSPACE
+    L.lib().ltm_plan_destroy(h)
+
+
+def test_binding_fails_loudly_without_library(L, monkeypatch, tmp_path):
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        L.lib()

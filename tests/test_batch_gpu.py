@@ -1,0 +1,143 @@
+"""Batched persistent sweep, its hipGraph replay and the autotuner.
+
+* the batch forward/adjoint equal the per-plan entry points (same samples;
+  only FP64 summation order may differ) and the FP64 oracle (1e-5);
+* a captured graph replays several times, with eager work and changed
+  inputs in between, and every replay equals the eager sweep;
+* every tiling the autotuner may pick passes parity before it is timed.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1812_03358_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def ltm():
+    from paper_1812_03358_amd import ltm as L
+    L.lib()
+    return L
+
+
+def _frames():
+    return [
+        (W.grid((20, 24, 18), 6.0), [W.plenoptic_camera(96, 6, (2, 2), 37, phi_deg=p)
+                                     for p in (0.0, 30.0)], W.flame(24, seed=1)[:18, :24, :20]),
+        (W.grid(16, 10.0), [W.plenoptic_camera(64, 4, (2, 2), 32, phi_deg=60.0)], W.flame(16, seed=2)),
+        (W.grid((17, 13, 11), 0.15), [W.single_lens_camera(50, (3, 2), 29, det_v=37)],
+         W.uniform_random((11, 13, 17), seed=3)),
+    ]
+
+
+def _setup(ltm, frames):
+    plans, xs, ys, xts = [], [], [], []
+    for g, cams, vol in frames:
+        p = ltm.Plan(g, cams)
+        plans.append(p)
+        xs.append(torch.from_numpy(np.ascontiguousarray(vol, np.float32).reshape(-1)).cuda())
+        ys.append(torch.zeros(p.n_meas, device="cuda"))
+        xts.append(torch.zeros(p.n_voxels, device="cuda"))
+    return plans, xs, ys, xts
+
+
+def test_batch_equals_per_plan_and_oracle(orc, ltm):
+    frames = _frames()
+    plans, xs, ys, xts = _setup(ltm, frames)
+    b = ltm.Batch(plans, xs, ys, xts)
+    b.sweep()
+    torch.cuda.synchronize()
+    for (g, cams, vol), p, x, y, xt in zip(frames, plans, xs, ys, xts):
+        y1 = p.project(x)
+        x1 = p.backproject(y)
+        assert rel_l2(y.cpu().numpy(), y1.cpu().numpy()) < 1e-7
+        assert rel_l2(xt.cpu().numpy(), x1.cpu().numpy()) < 1e-7
+        ref_y = orc.project(g, cams, np.asarray(vol, np.float64).reshape(-1))
+        ref_x = orc.backproject(g, cams, y.cpu().numpy().astype(np.float64))
+        assert rel_l2(y.cpu().numpy(), ref_y) < 1e-5
+        assert rel_l2(xt.cpu().numpy(), ref_x) < 1e-5
+
+
+def test_graph_replay_matches_eager(ltm):
+    frames = _frames()
+    plans, xs, ys, xts = _setup(ltm, frames)
+    b = ltm.Batch(plans, xs, ys, xts)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b.sweep(s)
+    s.synchronize()
+    eager_y = [y.clone() for y in ys]
+    eager_x = [x.clone() for x in xts]
+    b.capture(s)
+    for rep in range(4):
+        for y, x in zip(ys, xts):
+            y.fill_(-1.0)
+            x.fill_(-1.0)
+        torch.cuda.synchronize()
+        b.replay(s)
+        s.synchronize()
+        for y, x, ey, ex in zip(ys, xts, eager_y, eager_x):
+            assert rel_l2(y.cpu().numpy(), ey.cpu().numpy()) < 1e-7, rep
+            assert rel_l2(x.cpu().numpy(), ex.cpu().numpy()) < 1e-7, rep
+        # eager work between replays
+        plans[0].project(xs[0])
+        torch.cuda.synchronize()
+    # the graph reads its buffers at replay time: a new volume gives new images
+    xs[1].mul_(2.0)
+    b.replay(s)
+    s.synchronize()
+    assert rel_l2(ys[1].cpu().numpy(), 2.0 * eager_y[1].cpu().numpy()) < 1e-6
+
+
+def test_batched_frames_full_size_subset(orc, ltm):
+    # one frame of each size of the 48-frame workload, four cameras each
+    frames = []
+    seen = set()
+    for f in W.config_batched():
+        n = f["grid"]["nx"]
+        if n in seen:
+            continue
+        seen.add(n)
+        frames.append((f["grid"], f["cameras"], W.flame(n, f["volume_seed"])))
+    plans, xs, ys, xts = _setup(ltm, frames)
+    b = ltm.Batch(plans, xs, ys, xts)
+    b.sweep()
+    torch.cuda.synchronize()
+    for (g, cams, vol), y, xt in zip(frames, ys, xts):
+        ref_y = orc.project(g, cams, np.asarray(vol, np.float64).reshape(-1))
+        ref_x = orc.backproject(g, cams, y.cpu().numpy().astype(np.float64))
+        e1, e2 = rel_l2(y.cpu().numpy(), ref_y), rel_l2(xt.cpu().numpy(), ref_x)
+        print(g["nx"], e1, e2, flush=True)
+        assert e1 < 1e-5 and e2 < 1e-5
+
+
+def test_autotuner_candidates_pass_parity(orc, ltm):
+    from paper_1812_03358_amd import autotune
+    g = W.grid((20, 24, 18), 6.0)
+    cams = [W.plenoptic_camera(96, 6, (2, 2), 37, phi_deg=30.0)]
+    vol = W.flame(24, seed=1)[:18, :24, :20]
+    plan = ltm.Plan(g, cams)
+    x = torch.from_numpy(np.ascontiguousarray(vol).reshape(-1)).cuda()
+    y = torch.from_numpy(W.uniform_random(96 * 96, seed=4)).cuda()
+    ref_y = orc.project(g, cams, np.asarray(vol, np.float64).reshape(-1))
+    ref_x = orc.backproject(g, cams, y.cpu().numpy().astype(np.float64))
+    for d, ref, inp in ((0, ref_y, x), (1, ref_x, y)):
+        for cand in autotune.candidates(plan, 0, d):
+            try:
+                plan.set_tiling(d, 0, cand)
+            except ltm.LtmError:
+                continue
+            out = plan.project(x) if d == 0 else plan.backproject(y)
+            assert rel_l2(out.cpu().numpy(), ref) < 1e-5, cand
+    res = autotune.autotune_plan(plan, x, y, reps=2)
+    assert all(r["ms"] <= r["default_ms"] for r in res)
+    assert rel_l2(plan.project(x).cpu().numpy(), ref_y) < 1e-5
