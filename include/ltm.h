@@ -91,8 +91,11 @@ typedef struct ltm_camera {
 /* How one camera's rays are grouped into workgroups.  A tile is a block of
  * tile_u x tile_v lenslets (for single-lens cameras, blocks of
  * block_u x block_v pixels play the lenslets' role).  Its pixels are split
- * over `splits` workgroups; order 0 puts one lenslet's pixels on adjacent
- * lanes, order 1 walks adjacent lanes across lenslets.  Each workgroup
+ * over `splits` workgroups.  `order` holds flags: bit 0 clear puts one
+ * lenslet's pixels on adjacent lanes, set walks adjacent lanes across
+ * lenslets; bit 1 stops lanes from starting their angular-sample loop at
+ * different samples; bit 2 (adjoint) accumulates the brick in FP32 before the
+ * FP64 flush; bit 3 (adjoint) staggers the lanes' walks along their rays.  Each workgroup
  * marches its rays through consecutive slabs of chunk_mm camera depth,
  * staging the voxels the slab's rays touch in an LDS brick of at most
  * brick_floats floats (a slab whose brick does not fit uses global memory).
@@ -261,6 +264,72 @@ ltm_status ltm_batch_sweep(ltm_batch* batch, void* stream);
  * graph owned by the batch; replay it with ltm_batch_graph_launch. */
 ltm_status ltm_batch_graph_capture(ltm_batch* batch, void* stream);
 ltm_status ltm_batch_graph_launch(ltm_batch* batch, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Learned warm start: building blocks of a 3-D convolutional encoder-decoder
+ * that maps A^T y to a starting volume for the solver (an addition to the
+ * paper's method; the zero-start solver remains the reference).
+ * Activations are BF16 channels-last [d][h][w][c] (uint16 storage); weights
+ * keep an FP32 master copy [cout][taps * cin] (tap = dz*9 + dy*3 + dx,
+ * offsets -1..1, ci fastest) packed to BF16 by ltm_nn_pack_weights.
+ * Convolutions are "same" size with zero padding, run on MFMA with BF16
+ * operands and FP32 accumulation.  All pointers are device pointers; every
+ * call is asynchronous on `stream` and allocates nothing. */
+typedef struct ltm_nn_conv {
+    uint32_t ksize;       /* 1 or 3 */
+    uint32_t d, h, w;     /* output grid */
+    uint32_t c0, c1;      /* input channels read from in0, then in1 (concatenation); c1 may be 0.
+                             Multiples of 8, or c0 = 1 alone */
+    uint32_t cout;        /* output channels, <= 128 */
+    uint32_t upsample;    /* 1: the input grid is the output grid halved (nearest 2x upsampling) */
+    uint32_t relu;        /* 1: ReLU after the bias */
+    uint32_t out_f32;     /* 1: FP32 outputs, else BF16 */
+    uint32_t split;       /* output channels [0, split) -> out, [split, cout) -> out2 */
+    uint32_t reserved;
+} ltm_nn_conv;
+
+/* Element counts of the two packed BF16 weight layouts of a layer. */
+ltm_status ltm_nn_packed_sizes(uint32_t cout, uint32_t cin, uint32_t ksize, uint64_t* fwd_elems,
+                               uint64_t* bwd_elems);
+/* FP32 master weights -> packed forward (and, if w_bwd != NULL, input-gradient) BF16 layouts. */
+ltm_status ltm_nn_pack_weights(const float* w, uint32_t cout, uint32_t cin, uint32_t ksize,
+                               uint16_t* w_fwd, uint16_t* w_bwd, void* stream);
+/* out = act(conv(concat(in0, in1)) + bias). */
+ltm_status ltm_nn_conv3d_forward(const ltm_nn_conv* c, const uint16_t* in0, const uint16_t* in1,
+                                 const uint16_t* w_fwd, const float* bias, void* out, void* out2,
+                                 void* stream);
+/* Input gradient of the conv described by c: dx0 (c0 channels) and dx1 (c1
+ * channels) in FP32, from dy (BF16, the gradient at the pre-activation).
+ * For an upsampling conv the result is on the output grid: reduce it with
+ * ltm_nn_upsample2_backward. */
+ltm_status ltm_nn_conv3d_dgrad(const ltm_nn_conv* c, const uint16_t* dy, const uint16_t* w_bwd,
+                               float* dx0, float* dx1, void* stream);
+/* dw += weight gradient (FP32 [cout][taps * cin]) from the layer input and dy. */
+ltm_status ltm_nn_conv3d_wgrad(const ltm_nn_conv* c, const uint16_t* in0, const uint16_t* in1,
+                               const uint16_t* dy, float* dw, void* stream);
+/* 2x2x2 max pooling of a [d][h][w][c] grid; arg records the winning child. */
+ltm_status ltm_nn_maxpool2(const uint16_t* x, uint16_t* y, uint8_t* arg, uint32_t d, uint32_t h,
+                           uint32_t w, uint32_t c, void* stream);
+/* dx += the pooled gradient routed to the winning children (dx on the fine grid). */
+ltm_status ltm_nn_maxpool2_backward(const float* dy, const uint8_t* arg, float* dx, uint32_t d,
+                                    uint32_t h, uint32_t w, uint32_t c, void* stream);
+/* Backward of nearest 2x upsampling: d_low (= or +=) sum over each 2x2x2 block of d_high;
+ * d, h, w are the fine grid. */
+ltm_status ltm_nn_upsample2_backward(const float* d_high, float* d_low, uint32_t d, uint32_t h,
+                                     uint32_t w, uint32_t c, uint32_t accumulate, void* stream);
+/* g = d_out * (out > 0) (or d_out when relu = 0) as BF16; d_bias += per-channel sums (may be NULL). */
+ltm_status ltm_nn_relu_backward(const float* d_out, const uint16_t* out, uint32_t relu, uint16_t* g,
+                                float* d_bias, uint64_t n, uint32_t c, void* stream);
+/* loss += mean((x - target)^2) (FP64 scalar), grad = its gradient through a final ReLU. */
+ltm_status ltm_nn_mse(const float* x, const float* target, float* grad, double* loss, uint64_t n,
+                      void* stream);
+/* One bias-corrected Adam step (step >= 1) on FP32 weights; g is cleared. */
+ltm_status ltm_nn_adam(float* w, float* g, float* m, float* v, uint64_t n, double lr, double beta1,
+                       double beta2, double eps, uint32_t step, void* stream);
+/* y = x / max|x| as BF16 (the network input from A^T y); scratch: one uint32. */
+ltm_status ltm_nn_prep_input(const float* x, uint16_t* y, uint32_t* scratch, uint64_t n, void* stream);
+/* a += b (FP32). */
+ltm_status ltm_nn_add(float* a, const float* b, uint64_t n, void* stream);
 
 #ifdef __cplusplus
 }

@@ -58,6 +58,8 @@ struct CamDev {
     // tiling
     int tile_u, tile_v, order, splits;
     int rotate;           // lanes start their aperture-sample loop at lane mod R
+    int adj_f32;          // adjoint: FP32 LDS brick (flushed into the FP64 accumulator)
+    int skew;             // adjoint: lanes start their sample walk at staggered offsets
     int items, items_per_split, tiles_u, tiles_v, n_tiles;
     int brick_cap;        // LDS brick capacity in voxels (FP32 forward, FP64 adjoint)
     int max_chunks;

@@ -1,0 +1,495 @@
+// gfx950 kernels of the learned warm start: a 3-D convolutional
+// encoder-decoder that maps A^T y to a starting volume for the solver.
+//
+// Activations are channels-last BF16 [D][H][W][C]; weights keep an FP32
+// master copy [Cout][K] with K = tap * Cin + ci (tap = dz*9 + dy*3 + dx for
+// 3x3x3, offsets -1..1, zero padding), packed to BF16 for the MFMA kernels.
+//
+// Convolution = implicit GEMM on v_mfma_f32_16x16x32_bf16 (FP32 accumulate):
+// rows are output voxels, columns output channels, K runs over (tap, ci).
+// Operand lane layout of the 16x16x32 instruction: lane l supplies
+// A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16], j = 0..7, and
+// holds D[4 (l / 16) + i][l % 16], i = 0..3.
+#include "ltm_internal.h"
+#include "ltm_nn.h"
+
+namespace ltm {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16;
+
+__device__ __forceinline__ float bf2f(u16 v) { return __uint_as_float((unsigned)v << 16); }
+
+__device__ __forceinline__ u16 f2bf(float f)
+{
+    // round to nearest even (finite inputs); NaN stays NaN
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (u16)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (u16)(u >> 16);
+}
+
+union Frag {
+    bf16x8 v;
+    uint4 q;
+    u16 h[8];
+};
+
+// ---------------------------------------------------------------- conv forward
+// One workgroup: 4 waves x MT tiles of 16 output voxels (flattened index),
+// all NT x 16 output channels.  Input channels come from in0 (c0 channels)
+// then in1 (c1 channels, the concatenated skip); the input grid is the
+// output grid >> up (nearest upsampling fused into the read).
+template <int KS, bool CIN1, int NT, int MT>
+__global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, kg = lane >> 4;
+    const int V = a.D * a.H * a.W;
+    const int Din = a.D >> a.up, Hin = a.H >> a.up, Win = a.W >> a.up;
+    const int cin = a.c0 + a.c1;
+    const int taps = KS * KS * KS;
+    const int vbase = (blockIdx.x * 4 + wave) * (16 * MT);
+
+    int vz[MT], vy[MT], vx[MT];
+    bool vin[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        const int v = vbase + m * 16 + r;
+        vin[m] = v < V;
+        const int vv = vin[m] ? v : 0;
+        vx[m] = vv % a.W;
+        vy[m] = (vv / a.W) % a.H;
+        vz[m] = vv / (a.W * a.H);
+    }
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = 0; k0 < a.Kp; k0 += 32) {
+        const int kk = k0 + 8 * kg;
+        Frag A[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            A[m].q = uint4{0u, 0u, 0u, 0u};
+            if (!vin[m]) continue;
+            if (CIN1) {
+                // one input channel: the 8 K values are 8 taps
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int tap = kk + j;
+                    if (tap >= taps) continue;
+                    const int dz = KS == 3 ? tap / 9 - 1 : 0, dy = KS == 3 ? (tap / 3) % 3 - 1 : 0,
+                              dx = KS == 3 ? tap % 3 - 1 : 0;
+                    const int z = vz[m] + dz, y = vy[m] + dy, x = vx[m] + dx;
+                    if (z < 0 || z >= a.D || y < 0 || y >= a.H || x < 0 || x >= a.W) continue;
+                    const size_t src = ((size_t)(z >> a.up) * Hin + (y >> a.up)) * Win + (x >> a.up);
+                    A[m].h[j] = a.in0[src];
+                }
+            } else {
+                const int tap = kk / cin, ci = kk - tap * cin;
+                if (tap >= taps) continue;
+                const int dz = KS == 3 ? tap / 9 - 1 : 0, dy = KS == 3 ? (tap / 3) % 3 - 1 : 0,
+                          dx = KS == 3 ? tap % 3 - 1 : 0;
+                const int z = vz[m] + dz, y = vy[m] + dy, x = vx[m] + dx;
+                if (z < 0 || z >= a.D || y < 0 || y >= a.H || x < 0 || x >= a.W) continue;
+                const size_t src = ((size_t)(z >> a.up) * Hin + (y >> a.up)) * Win + (x >> a.up);
+                if (ci < a.c0)
+                    A[m].q = *reinterpret_cast<const uint4*>(a.in0 + src * a.c0 + ci);
+                else
+                    A[m].q = *reinterpret_cast<const uint4*>(a.in1 + src * a.c1 + (ci - a.c0));
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            Frag B;
+            B.q = *reinterpret_cast<const uint4*>(a.wt + (size_t)(t * 16 + r) * a.Kp + kk);
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+                acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[m].v, B.v, acc[m][t], 0, 0, 0);
+        }
+    }
+    // epilogue: bias, ReLU, store (BF16 or FP32, optionally split in two
+    // channel ranges for the input gradient of a concatenation)
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int co = t * 16 + r;
+            if (co >= a.cout) continue;
+            const float b = a.bias ? a.bias[co] : 0.0f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int v = vbase + m * 16 + 4 * kg + i;
+                if (v >= V) continue;
+                float val = acc[m][t][i] + b;
+                if (a.relu) val = fmaxf(val, 0.0f);
+                if (co < a.split) {
+                    const size_t o = (size_t)v * a.split + co;
+                    if (a.out_f32) reinterpret_cast<float*>(a.out)[o] = val;
+                    else reinterpret_cast<u16*>(a.out)[o] = f2bf(val);
+                } else {
+                    const int c2 = a.cout - a.split;
+                    const size_t o = (size_t)v * c2 + (co - a.split);
+                    if (a.out_f32) reinterpret_cast<float*>(a.out2)[o] = val;
+                    else reinterpret_cast<u16*>(a.out2)[o] = f2bf(val);
+                }
+            }
+        }
+}
+
+// ---------------------------------------------------------------- wgrad
+// dW[co][k] += sum_v dY[v][co] X_k[v], k = tap * Cin + ci, X_k the input
+// shifted by the tap (and upsampled when up = 1).  MFMA rows are output
+// channels, columns are k, the reduction runs over 32 voxels of one output
+// z-slice at a time.  A workgroup's 4 waves own 4 (co, k) tiles of one slice
+// and add them into the FP32 gradient with atomics.
+template <int KS>
+__global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, kg = lane >> 4;
+    const int n_co = (a.cout + 15) / 16;
+    const int n_k = (a.K + 15) / 16;
+    const int tile = blockIdx.x * 4 + wave;
+    if (tile >= n_co * n_k) return;
+    const int cot = tile % n_co, kt = tile / n_co;
+    const int z = blockIdx.y;
+    const int HW = a.H * a.W;
+    const int Hin = a.H >> a.up, Win = a.W >> a.up;
+    const int cin = a.c0 + a.c1;
+    const int co = cot * 16 + r;           // A row of this lane
+    const int k = kt * 16 + r;             // B column of this lane
+    const bool kvalid = k < a.K;
+    const int tap = kvalid ? k / cin : 0, ci = kvalid ? k - tap * cin : 0;
+    const int dz = KS == 3 ? tap / 9 - 1 : 0, dy = KS == 3 ? (tap / 3) % 3 - 1 : 0,
+              dx = KS == 3 ? tap % 3 - 1 : 0;
+    const int zz = z + dz;
+    const bool zin = kvalid && zz >= 0 && zz < a.D;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int v0 = 0; v0 < HW; v0 += 32) {
+        Frag A, B;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int v = v0 + 8 * kg + j;
+            u16 av = 0, bv = 0;
+            if (v < HW) {
+                if (co < a.cout) av = a.dy[((size_t)z * HW + v) * a.cout + co];
+                const int y = v / a.W + dy, x = v % a.W + dx;
+                if (zin && y >= 0 && y < a.H && x >= 0 && x < a.W) {
+                    const size_t src = ((size_t)(zz >> a.up) * Hin + (y >> a.up)) * Win + (x >> a.up);
+                    bv = ci < a.c0 ? a.in0[src * a.c0 + ci] : a.in1[src * a.c1 + (ci - a.c0)];
+                }
+            }
+            A.h[j] = av;
+            B.h[j] = bv;
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.v, B.v, acc, 0, 0, 0);
+    }
+    // D[row = 4 kg + i][col = r]: row is the output channel, col is k
+    const int kc = kt * 16 + r;
+    if (kc >= a.K) return;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int c = cot * 16 + 4 * kg + i;
+        if (c < a.cout && acc[i] != 0.0f) unsafeAtomicAdd(&a.dw[(size_t)c * a.K + kc], acc[i]);
+    }
+}
+
+// ---------------------------------------------------------------- elementwise
+// Pack FP32 master weights [Cout][K] into the BF16 forward layout
+// [NT*16][Kp] and the input-gradient layout [Cin_pad][Kp'] (flipped taps,
+// in/out channels swapped), zero padded.
+__global__ void k_pack(const float* __restrict__ w, int cout, int cin, int taps, u16* __restrict__ wf,
+                       int rows_f, int kp_f, u16* __restrict__ wb, int rows_b, int kp_b)
+{
+    const int K = taps * cin;
+    const size_t nf = (size_t)rows_f * kp_f, nb = wb ? (size_t)rows_b * kp_b : 0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nf + nb;
+         i += (size_t)gridDim.x * blockDim.x) {
+        if (i < nf) {
+            const int row = (int)(i / kp_f), k = (int)(i % kp_f);
+            wf[i] = (row < cout && k < K) ? f2bf(w[(size_t)row * K + k]) : (u16)0;
+        } else {
+            const size_t j = i - nf;
+            const int c = (int)(j / kp_b), kb = (int)(j % kp_b);   // c: input channel
+            u16 v = 0;
+            if (c < cin && kb < taps * cout) {
+                const int tb = kb / cout, o = kb - tb * cout;
+                const int t = taps - 1 - tb;                        // flipped tap
+                v = f2bf(w[(size_t)o * K + t * cin + c]);
+            }
+            wb[j] = v;
+        }
+    }
+}
+
+// y = 2x2x2 max of x (BF16, channels-last), arg = winning child 0..7.
+__global__ void k_maxpool(const u16* __restrict__ x, u16* __restrict__ y, unsigned char* __restrict__ arg,
+                          int D, int H, int W, int C)
+{
+    const int Do = D / 2, Ho = H / 2, Wo = W / 2;
+    const size_t n = (size_t)Do * Ho * Wo * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        const size_t v = i / C;
+        const int xo = (int)(v % Wo), yo = (int)((v / Wo) % Ho), zo = (int)(v / ((size_t)Wo * Ho));
+        float best = -INFINITY;
+        int bi = 0;
+        for (int q = 0; q < 8; ++q) {
+            const int z = 2 * zo + (q >> 2), yy = 2 * yo + ((q >> 1) & 1), xx = 2 * xo + (q & 1);
+            const float val = bf2f(x[(((size_t)z * H + yy) * W + xx) * C + c]);
+            if (val > best) {
+                best = val;
+                bi = q;
+            }
+        }
+        y[i] = f2bf(best);
+        arg[i] = (unsigned char)bi;
+    }
+}
+
+// dx[child] += dy at the winning child (FP32 accumulate into dx).
+__global__ void k_maxpool_bwd(const float* __restrict__ dy, const unsigned char* __restrict__ arg,
+                              float* __restrict__ dx, int D, int H, int W, int C)
+{
+    const int Do = D / 2, Ho = H / 2, Wo = W / 2;
+    const size_t n = (size_t)Do * Ho * Wo * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        const size_t v = i / C;
+        const int xo = (int)(v % Wo), yo = (int)((v / Wo) % Ho), zo = (int)(v / ((size_t)Wo * Ho));
+        const int q = arg[i];
+        const int z = 2 * zo + (q >> 2), yy = 2 * yo + ((q >> 1) & 1), xx = 2 * xo + (q & 1);
+        dx[(((size_t)z * H + yy) * W + xx) * C + c] += dy[i];
+    }
+}
+
+// dlow = sum of the 8 children of dhigh (backward of nearest 2x upsampling).
+__global__ void k_sumpool(const float* __restrict__ dh, float* __restrict__ dl, int D, int H, int W, int C,
+                          int accumulate)
+{
+    const int Do = D / 2, Ho = H / 2, Wo = W / 2;
+    const size_t n = (size_t)Do * Ho * Wo * C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        const size_t v = i / C;
+        const int xo = (int)(v % Wo), yo = (int)((v / Wo) % Ho), zo = (int)(v / ((size_t)Wo * Ho));
+        float s = 0.0f;
+        for (int q = 0; q < 8; ++q) {
+            const int z = 2 * zo + (q >> 2), yy = 2 * yo + ((q >> 1) & 1), xx = 2 * xo + (q & 1);
+            s += dh[(((size_t)z * H + yy) * W + xx) * C + c];
+        }
+        dl[i] = accumulate ? dl[i] + s : s;
+    }
+}
+
+// g = dOut * (out > 0) as BF16 (the MFMA operand) and its per-channel sum.
+__global__ void k_relu_mask(const float* __restrict__ dout, const u16* __restrict__ out, int relu,
+                            u16* __restrict__ g, float* __restrict__ dbias, size_t n, int C)
+{
+    extern __shared__ float sb[];
+    for (int c = threadIdx.x; c < C; c += blockDim.x) sb[c] = 0.0f;
+    __syncthreads();
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        float v = dout[i];
+        if (relu && !(bf2f(out[i]) > 0.0f)) v = 0.0f;
+        const u16 b = f2bf(v);
+        g[i] = b;
+        if (v != 0.0f) atomicAdd(&sb[i % C], bf2f(b));
+    }
+    __syncthreads();
+    if (dbias)
+        for (int c = threadIdx.x; c < C; c += blockDim.x)
+            if (sb[c] != 0.0f) unsafeAtomicAdd(&dbias[c], sb[c]);
+}
+
+// Loss 1/V sum (x - t)^2 of the network output (FP32) against the target,
+// and its gradient through the final ReLU.
+__global__ void k_mse(const float* __restrict__ x, const float* __restrict__ t, float* __restrict__ g,
+                      double* __restrict__ loss, size_t n)
+{
+    __shared__ double red[4];
+    double s = 0.0;
+    const float inv = 1.0f / (float)n;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const float d = x[i] - t[i];
+        s += (double)d * d;
+        g[i] = x[i] > 0.0f ? 2.0f * d * inv : 0.0f;
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) unsafeAtomicAdd(loss, (red[0] + red[1] + red[2] + red[3]) / (double)n);
+}
+
+// Adam on FP32 master weights (bias-corrected), gradients cleared after use.
+__global__ void k_adam(float* __restrict__ w, float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, size_t n, float lr, float b1, float b2, float eps,
+                       float c1, float c2)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        g[i] = 0.0f;
+    }
+}
+
+// Network input: A^T y scaled by 1 / max (max over the volume), as BF16.
+__global__ void k_absmax(const float* __restrict__ x, size_t n, unsigned int* __restrict__ out)
+{
+    float mval = 0.0f;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        mval = fmaxf(mval, fabsf(x[i]));
+    for (int o = 32; o > 0; o >>= 1) mval = fmaxf(mval, __shfl_xor(mval, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(mval));
+}
+
+__global__ void k_scale_to_bf16(const float* __restrict__ x, const unsigned int* __restrict__ mx,
+                                u16* __restrict__ y, size_t n)
+{
+    const float m = __uint_as_float(*mx);
+    const float s = m > 0.0f ? 1.0f / m : 0.0f;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] = f2bf(x[i] * s);
+}
+
+__global__ void k_add(float* __restrict__ a, const float* __restrict__ b, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        a[i] += b[i];
+}
+
+__global__ void k_fill_u32(unsigned int* p, size_t n, unsigned int v)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+unsigned nblocks(size_t n)
+{
+    size_t b = (n + 255) / 256;
+    return (unsigned)(b > 16384 ? 16384 : (b ? b : 1));
+}
+
+template <int KS, bool CIN1, int NT>
+hipError_t conv_mt(const ConvFwd& a, hipStream_t s)
+{
+    constexpr int MT = NT >= 8 ? 1 : (NT >= 4 ? 2 : 4);
+    const int V = a.D * a.H * a.W;
+    const int per_block = 4 * 16 * MT;
+    hipLaunchKernelGGL((k_conv_fwd<KS, CIN1, NT, MT>), dim3((V + per_block - 1) / per_block), dim3(256), 0,
+                       s, a);
+    return hipGetLastError();
+}
+
+template <int KS, bool CIN1>
+hipError_t conv_nt(const ConvFwd& a, int nt, hipStream_t s)
+{
+    switch (nt) {
+        case 1: return conv_mt<KS, CIN1, 1>(a, s);
+        case 2: return conv_mt<KS, CIN1, 2>(a, s);
+        case 4: return conv_mt<KS, CIN1, 4>(a, s);
+        case 8: return conv_mt<KS, CIN1, 8>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t nn_conv_fwd(const ConvFwd& a, int ks, hipStream_t s)
+{
+    const int nt = (a.cout + 15) / 16;
+    const int ntp = nt <= 1 ? 1 : (nt <= 2 ? 2 : (nt <= 4 ? 4 : 8));
+    const bool cin1 = (a.c0 + a.c1) == 1;
+    if (ks == 3) return cin1 ? conv_nt<3, true>(a, ntp, s) : conv_nt<3, false>(a, ntp, s);
+    return cin1 ? conv_nt<1, true>(a, ntp, s) : conv_nt<1, false>(a, ntp, s);
+}
+
+hipError_t nn_conv_wgrad(const ConvWgrad& a, int ks, hipStream_t s)
+{
+    const int tiles = ((a.cout + 15) / 16) * ((a.K + 15) / 16);
+    dim3 grid((tiles + 3) / 4, a.D);
+    if (ks == 3)
+        hipLaunchKernelGGL(k_conv_wgrad<3>, grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_conv_wgrad<1>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t nn_pack(const float* w, int cout, int cin, int taps, unsigned short* wf, int rows_f, int kp_f,
+                   unsigned short* wb, int rows_b, int kp_b, hipStream_t s)
+{
+    const size_t n = (size_t)rows_f * kp_f + (wb ? (size_t)rows_b * kp_b : 0);
+    hipLaunchKernelGGL(k_pack, dim3(nblocks(n)), dim3(256), 0, s, w, cout, cin, taps, wf, rows_f, kp_f, wb,
+                       rows_b, kp_b);
+    return hipGetLastError();
+}
+
+hipError_t nn_maxpool(const unsigned short* x, unsigned short* y, unsigned char* arg, int D, int H, int W, int C,
+                      hipStream_t s)
+{
+    hipLaunchKernelGGL(k_maxpool, dim3(nblocks((size_t)D * H * W * C / 8)), dim3(256), 0, s, x, y, arg, D, H, W, C);
+    return hipGetLastError();
+}
+
+hipError_t nn_maxpool_bwd(const float* dy, const unsigned char* arg, float* dx, int D, int H, int W, int C,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(k_maxpool_bwd, dim3(nblocks((size_t)D * H * W * C / 8)), dim3(256), 0, s, dy, arg, dx, D,
+                       H, W, C);
+    return hipGetLastError();
+}
+
+hipError_t nn_sumpool(const float* dh, float* dl, int D, int H, int W, int C, int accumulate, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sumpool, dim3(nblocks((size_t)D * H * W * C / 8)), dim3(256), 0, s, dh, dl, D, H, W, C,
+                       accumulate);
+    return hipGetLastError();
+}
+
+hipError_t nn_relu_mask(const float* dout, const unsigned short* out, int relu, unsigned short* g,
+                        float* dbias, size_t n, int C, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_relu_mask, dim3(nblocks(n)), dim3(256), C * sizeof(float), s, dout, out, relu, g, dbias,
+                       n, C);
+    return hipGetLastError();
+}
+
+hipError_t nn_mse(const float* x, const float* t, float* g, double* loss, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mse, dim3(nblocks(n)), dim3(256), 0, s, x, t, g, loss, n);
+    return hipGetLastError();
+}
+
+hipError_t nn_adam(float* w, float* g, float* m, float* v, size_t n, float lr, float b1, float b2, float eps,
+                   int step, hipStream_t s)
+{
+    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3(nblocks(n)), dim3(256), 0, s, w, g, m, v, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t nn_prep_input(const float* x, unsigned short* y, unsigned int* scratch, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, scratch, (size_t)1, 0u);
+    hipLaunchKernelGGL(k_absmax, dim3(nblocks(n)), dim3(256), 0, s, x, n, scratch);
+    hipLaunchKernelGGL(k_scale_to_bf16, dim3(nblocks(n)), dim3(256), 0, s, x, scratch, y, n);
+    return hipGetLastError();
+}
+
+hipError_t nn_add(float* a, const float* b, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_add, dim3(nblocks(n)), dim3(256), 0, s, a, b, n);
+    return hipGetLastError();
+}
+
+}  // namespace ltm

@@ -105,7 +105,7 @@ ltm_status check_tiling(const ltm_camera& c, const ltm_tiling& t)
         return fail(LTM_ERR_INVALID, "tiling sizes must be positive");
     if (c.kind == LTM_SINGLE_LENS && (t.block_u == 0 || t.block_v == 0))
         return fail(LTM_ERR_INVALID, "single-lens tiling needs block sizes");
-    if (t.order > 3) return fail(LTM_ERR_INVALID, "tiling order must be 0..3");
+    if (t.order > 15) return fail(LTM_ERR_INVALID, "tiling order flags must be 0..15");
     if (t.brick_floats > (uint32_t)kMaxBrickFloats)
         return fail(LTM_ERR_INVALID, "brick larger than 64 KiB of LDS");
     if (!(t.chunk_mm > 0) || !std::isfinite(t.chunk_mm))
@@ -236,6 +236,8 @@ void apply_tiling(const ltm_grid& g, const ltm_camera& c, const ltm_tiling& t, C
     d.tile_v = (int)t.tile_v;
     d.order = (int)t.order;
     d.rotate = (t.order & 2) ? 0 : 1;
+    d.adj_f32 = (t.order & 4) ? 1 : 0;
+    d.skew = (t.order & 8) ? 1 : 0;
     d.splits = (int)t.splits;
     d.items = d.tile_u * d.tile_v * d.ku * d.kv;
     d.items_per_split = (d.items + d.splits - 1) / d.splits;
@@ -292,7 +294,7 @@ CamDev bound_dev(const ltm_plan* p, const CamHost& c, int dir)
     CamDev d = c.dev;
     int nt, mc;
     apply_tiling(p->grid, c.desc, c.tiling[dir], d, nt, mc);
-    if (dir == LTM_ADJOINT) d.brick_cap /= 2;   // FP64 brick in the same LDS budget
+    if (dir == LTM_ADJOINT && !d.adj_f32) d.brick_cap /= 2;   // FP64 brick in the same LDS budget
     d.tiles = reinterpret_cast<const TileRec*>(p->ws + c.tiles_off[dir]);
     d.bricks = reinterpret_cast<const BrickRec*>(p->ws + c.bricks_off[dir]);
     d.y_off = c.y_off;

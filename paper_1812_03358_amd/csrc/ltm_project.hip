@@ -285,18 +285,20 @@ __device__ void stage_brick(const BrickRec& b, const int n[3], const float* __re
     }
 }
 
-__device__ void zero_brick(const BrickRec& b, double* brick)
+template <typename T>
+__device__ void zero_brick(const BrickRec& b, T* brick)
 {
     const int vol = b.dim[0] * b.dim[1] * b.dim[2];
-    for (int e = threadIdx.x; e < vol; e += kThreads) brick[e] = 0.0;
+    for (int e = threadIdx.x; e < vol; e += kThreads) brick[e] = (T)0;
 }
 
-__device__ void flush_brick(const BrickRec& b, const int n[3], double* brick, double* __restrict__ x)
+template <typename T>
+__device__ void flush_brick(const BrickRec& b, const int n[3], T* brick, double* __restrict__ x)
 {
     const int vol = b.dim[0] * b.dim[1] * b.dim[2];
     const float idx = 1.0f / (float)b.dim[0], idy = 1.0f / (float)b.dim[1];
     for (int e = threadIdx.x; e < vol; e += kThreads) {
-        const double v = brick[e];
+        const double v = (double)brick[e];
         if (v == 0.0) continue;
         int lx, ly, lz;
         brick_coords(e, b.dim[0], b.dim[1], idx, idy, lx, ly, lz);
@@ -357,8 +359,8 @@ __device__ __forceinline__ double gather_global(const March& mr, int m0, int m1,
     return acc;
 }
 
-template <typename Add>
-__device__ __forceinline__ void scatter8(double* p, size_t sx, size_t sxy, const Cell& s, float v,
+template <typename T, typename Add>
+__device__ __forceinline__ void scatter8(T* p, size_t sx, size_t sxy, const Cell& s, float v,
                                          Add add)
 {
     const float gx = 1.0f - s.f[0], gy = 1.0f - s.f[1], gz = 1.0f - s.f[2];
@@ -374,20 +376,29 @@ __device__ __forceinline__ void scatter8(double* p, size_t sx, size_t sxy, const
     add(p + sxy + sx + 1, s.f[0] * a11);
 }
 
+// Scatter one ray's samples [m0, m1) into the LDS brick.  With skew, lane
+// l walks the samples starting at offset (l mod 64) * count / 64 and wraps,
+// so rays of one narrow bundle are at different depths at any moment and
+// their LDS atomics do not collide on the same voxels.
+template <typename T>
 __device__ __forceinline__ void scatter_lds(const March& mr, int m0, int m1, const BrickRec& b,
-                                            double* brick, const float nm1[3], float v)
+                                            T* brick, const float nm1[3], float v, bool skew)
 {
     const float dx = (float)b.dim[0], dxy = (float)(b.dim[0] * b.dim[1]);
     const int sx = b.dim[0], sxy = b.dim[0] * b.dim[1];
     const float maxi = (float)(b.dim[0] * b.dim[1] * b.dim[2] - 1 - (1 + sx + sxy));
-    for (int m = m0; m < m1; ++m) {
+    const int cnt = m1 - m0;
+    int m = m0;
+    if (skew) m += (int)(((threadIdx.x & 63) * (unsigned)cnt) >> 6);
+    for (int k = 0; k < cnt; ++k) {
         const float fm = (float)m;
         const Cell s = cell_of(fmaf(fm, mr.st[0], mr.qs[0]), fmaf(fm, mr.st[1], mr.qs[1]),
                                fmaf(fm, mr.st[2], mr.qs[2]), nm1);
         const float fi = fmaf(s.i[2], dxy, fmaf(s.i[1], dx, s.i[0])) - b.base;
         const int i0 = (int)clampf(fi, 0.0f, maxi);
-        scatter8(brick + i0, (size_t)sx, (size_t)sxy, s, v,
-                 [](double* q, float a) { atomicAdd(q, (double)a); });
+        scatter8(brick + i0, (size_t)sx, (size_t)sxy, s, v, [](T* q, float a) { atomicAdd(q, (T)a); });
+        ++m;
+        m = m == m1 ? m0 : m;
     }
 }
 
@@ -500,10 +511,14 @@ __device__ void march_tile(const CamDev& c, int tile, const float* __restrict__ 
         const bool last = ch == t.n_chunks - 1;
         if (b.lds) {
             __syncthreads();
-            if (kAdj)
-                zero_brick(b, reinterpret_cast<double*>(m.brick));
-            else
+            if (kAdj) {
+                if (c.adj_f32)
+                    zero_brick(b, reinterpret_cast<float*>(m.brick));
+                else
+                    zero_brick(b, reinterpret_cast<double*>(m.brick));
+            } else {
                 stage_brick(b, c.n, in, reinterpret_cast<float*>(m.brick));
+            }
             __syncthreads();
         }
         for (int e = threadIdx.x; e < nrays; e += kThreads) {
@@ -524,15 +539,20 @@ __device__ void march_tile(const CamDev& c, int tile, const float* __restrict__ 
                 atomicAdd(&m.item[item], s * (double)r.w);
             } else {
                 const float v = (float)m.item[item] * r.w;
-                if (b.lds)
-                    scatter_lds(mr, m0, m1, b, reinterpret_cast<double*>(m.brick), nm1, v);
-                else
+                if (!b.lds)
                     scatter_global(mr, m0, m1, c.n, xacc, nm1, v);
+                else if (c.adj_f32)
+                    scatter_lds(mr, m0, m1, b, reinterpret_cast<float*>(m.brick), nm1, v, c.skew);
+                else
+                    scatter_lds(mr, m0, m1, b, reinterpret_cast<double*>(m.brick), nm1, v, c.skew);
             }
         }
         if (kAdj && b.lds) {
             __syncthreads();
-            flush_brick(b, c.n, reinterpret_cast<double*>(m.brick), xacc);
+            if (c.adj_f32)
+                flush_brick(b, c.n, reinterpret_cast<float*>(m.brick), xacc);
+            else
+                flush_brick(b, c.n, reinterpret_cast<double*>(m.brick), xacc);
         }
     }
     if (!kAdj) {
@@ -677,7 +697,7 @@ size_t march_lds_bytes(const CamDev& c, int dir)
 {
     const size_t list_bytes = ((size_t)c.items_per_split * c.ru * c.rv * 4 + 15) & ~size_t(15);
     const size_t item_bytes = ((size_t)c.items_per_split * 8 + 15) & ~size_t(15);
-    const size_t brick_bytes = (size_t)c.brick_cap * (dir == LTM_ADJOINT ? 8 : 4);
+    const size_t brick_bytes = (size_t)c.brick_cap * ((dir == LTM_ADJOINT && !c.adj_f32) ? 8 : 4);
     return list_bytes + item_bytes + brick_bytes;
 }
 

@@ -67,6 +67,12 @@ class SolverParams(ctypes.Structure):
                 ("nu", ctypes.c_double), ("c_r", ctypes.c_double)]
 
 
+class ConvDesc(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint32) for k in
+                ("ksize", "d", "h", "w", "c0", "c1", "cout", "upsample", "relu", "out_f32", "split",
+                 "reserved")]
+
+
 _lib = None
 
 # name -> (restype, argtypes)
@@ -109,6 +115,24 @@ _SIGS = {
     "ltm_batch_graph_launch": (ctypes.c_int, [_VP, _VP]),
     "ltm_reg_grad_add": (ctypes.c_int, [ctypes.POINTER(Grid), _U32, _D, _D, _VP, _VP, _VP]),
 }
+
+
+_NN_SIGS = {
+    "ltm_nn_packed_sizes": (ctypes.c_int, [_U32, _U32, _U32, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
+    "ltm_nn_pack_weights": (ctypes.c_int, [_VP, _U32, _U32, _U32, _VP, _VP, _VP]),
+    "ltm_nn_conv3d_forward": (ctypes.c_int, [ctypes.POINTER(ConvDesc), _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "ltm_nn_conv3d_dgrad": (ctypes.c_int, [ctypes.POINTER(ConvDesc), _VP, _VP, _VP, _VP, _VP]),
+    "ltm_nn_conv3d_wgrad": (ctypes.c_int, [ctypes.POINTER(ConvDesc), _VP, _VP, _VP, _VP, _VP]),
+    "ltm_nn_maxpool2": (ctypes.c_int, [_VP, _VP, _VP, _U32, _U32, _U32, _U32, _VP]),
+    "ltm_nn_maxpool2_backward": (ctypes.c_int, [_VP, _VP, _VP, _U32, _U32, _U32, _U32, _VP]),
+    "ltm_nn_upsample2_backward": (ctypes.c_int, [_VP, _VP, _U32, _U32, _U32, _U32, _U32, _VP]),
+    "ltm_nn_relu_backward": (ctypes.c_int, [_VP, _VP, _U32, _VP, _VP, _U64, _U32, _VP]),
+    "ltm_nn_mse": (ctypes.c_int, [_VP, _VP, _VP, _VP, _U64, _VP]),
+    "ltm_nn_adam": (ctypes.c_int, [_VP, _VP, _VP, _VP, _U64, _D, _D, _D, _D, _U32, _VP]),
+    "ltm_nn_prep_input": (ctypes.c_int, [_VP, _VP, _VP, _U64, _VP]),
+    "ltm_nn_add": (ctypes.c_int, [_VP, _VP, _U64, _VP]),
+}
+_SIGS.update(_NN_SIGS)
 
 
 def lib():

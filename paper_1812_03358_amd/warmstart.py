@@ -1,0 +1,139 @@
+"""Learned warm start for the reconstruction: training and evaluation.
+
+Training pairs are made by the projector itself: a seeded flame volume x
+(generated on host worker processes), its noiseless images y = A x from the
+two-camera plenoptic plan, and the network input A^T y / max.  The loss is
+the mean squared error between the network output and x; Adam updates the
+FP32 master weights.  Every arithmetic step runs in libltm kernels.
+
+Evaluation: for held-out volumes, the wall-clock time from "images on the
+device, plan bound" to a confirmed relative data residual <= target, for
+the plain solver started at zero and for the solver started at the network
+output (time includes A^T y and the network forward).  Both solves are the
+same FISTA (beta = nu = 0, nonnegativity only).
+"""
+from __future__ import annotations
+
+import multiprocessing as mp
+import time
+
+import numpy as np
+import torch
+
+from . import ltm as _ltm
+from . import nn as _nn
+from . import workloads as W
+
+
+def _flame(args):
+    n, seed = args
+    return seed, W.flame(n, seed)
+
+
+class VolumeStream:
+    """Seeded flame volumes produced by host worker processes, in order."""
+
+    def __init__(self, n, seeds, workers=8):
+        self.n = n
+        self.seeds = list(seeds)
+        ctx = mp.get_context("fork")
+        self.pool = ctx.Pool(workers)
+        self.it = self.pool.imap(_flame, [(n, s) for s in self.seeds], chunksize=1)
+
+    def __iter__(self):
+        for _ in self.seeds:
+            yield next(self.it)
+
+    def close(self):
+        self.pool.terminate()
+        self.pool.join()
+
+
+def make_plan(device="cuda"):
+    cfg = W.config_warm_start()
+    return _ltm.Plan(cfg["grid"], cfg["cameras"], device=device), cfg
+
+
+def infer(net, plan, y, n, stream=None):
+    """Network estimate of the volume from images y (FP32 on the device)."""
+    aty = plan.backproject(y)
+    inp = net.prep_input(aty, stream)
+    return net.forward(inp, n, n, n, stream)
+
+
+def train(net, plan, n, seeds, lr=1e-3, time_limit=None, workers=8, log=None):
+    """One pass over the given seeds (or until time_limit seconds)."""
+    stream = VolumeStream(n, seeds, workers)
+    t0 = time.perf_counter()
+    losses = []
+    count = 0
+    try:
+        for seed, vol in stream:
+            x = torch.from_numpy(vol.reshape(-1)).to(net.device)
+            y = plan.project(x)
+            out = infer(net, plan, y, n)
+            loss, g = net.loss_and_grad(x)
+            net.backward(g)
+            net.step(lr)
+            count += 1
+            if count % 25 == 0 or count == 1:
+                losses.append((count, float(loss)))
+                if log:
+                    log(f"train step {count} seed {seed} loss {float(loss):.4e} "
+                        f"{time.perf_counter() - t0:.1f}s")
+            if time_limit and time.perf_counter() - t0 > time_limit:
+                break
+    finally:
+        stream.close()
+    torch.cuda.synchronize()
+    return {"steps": count, "seconds": time.perf_counter() - t0, "losses": losses}
+
+
+def solve_to(plan, y, x0=None, rho_target=1e-3, max_iter=5000, check_every=10, prelude=None):
+    """FISTA (beta = nu = 0) from x0 (None: zero) until rho <= target.
+
+    Wall-clock from the call (plan bound, y on the device) to the confirmed
+    residual of the iterate x; `prelude` (a callable returning x0) is timed
+    inside.  Returns dict(iterations, seconds, rho, converged)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if prelude is not None:
+        x0 = prelude()
+    s = _ltm.Solver(plan, y, momentum=True)
+    s.reset(x0)
+    it = 0
+    rho = float("inf")
+    converged = False
+    while it < max_iter:
+        s.step(check_every)
+        it += check_every
+        rho_z, _ = s.residual()
+        if rho_z <= rho_target:
+            rho = s.residual_x()
+            if rho <= rho_target:
+                converged = True
+                break
+    if not converged:
+        rho = s.residual_x()
+    torch.cuda.synchronize()
+    return {"iterations": it, "seconds": time.perf_counter() - t0, "rho": rho, "converged": converged}
+
+
+def compare(net, plan, n, seeds, rho_target=1e-3, max_iter=5000, check_every=10, log=None):
+    """Zero start vs warm start on held-out seeds."""
+    rows = []
+    for seed in seeds:
+        x = torch.from_numpy(W.flame(n, seed).reshape(-1)).to(net.device)
+        y = plan.project(x).clone()
+        zero = solve_to(plan, y, None, rho_target, max_iter, check_every)
+        warm = solve_to(plan, y, None, rho_target, max_iter, check_every,
+                        prelude=lambda: infer(net, plan, y, n).contiguous())
+        x0 = infer(net, plan, y, n)
+        err0 = float(torch.linalg.norm(x0 - x) / torch.linalg.norm(x))
+        row = {"seed": seed, "zero": zero, "warm": warm, "net_rel_error": err0}
+        rows.append(row)
+        if log:
+            log(f"seed {seed}: zero {zero['iterations']} it {zero['seconds']:.2f}s rho {zero['rho']:.2e} | "
+                f"warm {warm['iterations']} it {warm['seconds']:.2f}s rho {warm['rho']:.2e} | "
+                f"network error {err0:.3f}")
+    return rows
