@@ -124,18 +124,35 @@ __device__ __forceinline__ float clampf(float v, float lo, float hi)
 
 // Trilinear cell of sample position q: clamp to [0, n-1], cell origin
 // i = min(floor(q), n-2) and fraction f = q - i (identical in every kernel).
+// floor(clamp(q, 0, nextbelow(n-1))) equals min(floor(clamp(q, 0, n-1)), n-2)
+// for every q, without a separate min.
 struct Cell {
     float i[3], f[3];
 };
 
-__device__ __forceinline__ Cell cell_of(float qx, float qy, float qz, const float nm1[3])
+struct Bounds {
+    float nm1[3], nm1m[3];   // n - 1 and the largest float below it
+};
+
+__device__ __forceinline__ Bounds bounds_of(const int n[3])
+{
+    Bounds b;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        b.nm1[k] = (float)(n[k] - 1);
+        b.nm1m[k] = __int_as_float(__float_as_int(b.nm1[k]) - 1);
+    }
+    return b;
+}
+
+__device__ __forceinline__ Cell cell_of(float qx, float qy, float qz, const Bounds& bd)
 {
     Cell s;
     const float q[3] = {qx, qy, qz};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const float qc = clampf(q[k], 0.0f, nm1[k]);
-        s.i[k] = fminf(floorf(qc), nm1[k] - 1.0f);
+        const float qc = clampf(q[k], 0.0f, bd.nm1[k]);
+        s.i[k] = floorf(clampf(q[k], 0.0f, bd.nm1m[k]));
         s.f[k] = qc - s.i[k];
     }
     return s;
@@ -324,37 +341,44 @@ __device__ __forceinline__ March march_of(const Ray& r)
 }
 
 __device__ __forceinline__ double gather_lds(const March& mr, int m0, int m1, const BrickRec& b,
-                                             const float* brick, const float nm1[3])
+                                             const float* brick, const Bounds& bd)
 {
     const float dx = (float)b.dim[0], dxy = (float)(b.dim[0] * b.dim[1]);
     const int sx = b.dim[0], sxy = b.dim[0] * b.dim[1];
     const float maxi = (float)(b.dim[0] * b.dim[1] * b.dim[2] - 1 - (1 + sx + sxy));
     double acc = 0.0;
-    for (int m = m0; m < m1; ++m) {
-        const float fm = (float)m;
-        const Cell s = cell_of(fmaf(fm, mr.st[0], mr.qs[0]), fmaf(fm, mr.st[1], mr.qs[1]),
-                               fmaf(fm, mr.st[2], mr.qs[2]), nm1);
-        const float fi = fmaf(s.i[2], dxy, fmaf(s.i[1], dx, s.i[0])) - b.base;
-        const int i0 = (int)clampf(fi, 0.0f, maxi);
-        const float* p = brick + i0;
-        acc += (double)tri(p[0], p[1], p[sx], p[sx + 1], p[sxy], p[sxy + 1], p[sxy + sx],
-                           p[sxy + sx + 1], s);
+    // samples are summed in FP32 groups of up to 8, each group added in FP64
+    for (int g0 = m0; g0 < m1; g0 += 8) {
+        const float fend = (float)min(g0 + 8, m1);
+        float part = 0.0f;
+        for (float fm = (float)g0; fm < fend; fm += 1.0f) {
+            const Cell s = cell_of(fmaf(fm, mr.st[0], mr.qs[0]), fmaf(fm, mr.st[1], mr.qs[1]),
+                                   fmaf(fm, mr.st[2], mr.qs[2]), bd);
+            const float fi = fmaf(s.i[2], dxy, fmaf(s.i[1], dx, s.i[0])) - b.base;
+            const int i0 = (int)clampf(fi, 0.0f, maxi);
+            const float* p = brick + i0;
+            part += tri(p[0], p[1], p[sx], p[sx + 1], p[sxy], p[sxy + 1], p[sxy + sx], p[sxy + sx + 1], s);
+        }
+        acc += (double)part;
     }
     return acc;
 }
 
 __device__ __forceinline__ double gather_global(const March& mr, int m0, int m1, const int n[3],
-                                                const float* __restrict__ x, const float nm1[3])
+                                                const float* __restrict__ x, const Bounds& bd)
 {
     const size_t sx = (size_t)n[0], sxy = (size_t)n[0] * n[1];
     double acc = 0.0;
-    for (int m = m0; m < m1; ++m) {
-        const float fm = (float)m;
-        const Cell s = cell_of(fmaf(fm, mr.st[0], mr.qs[0]), fmaf(fm, mr.st[1], mr.qs[1]),
-                               fmaf(fm, mr.st[2], mr.qs[2]), nm1);
-        const float* p = x + gindex(n, (int)s.i[0], (int)s.i[1], (int)s.i[2]);
-        acc += (double)tri(p[0], p[1], p[sx], p[sx + 1], p[sxy], p[sxy + 1], p[sxy + sx],
-                           p[sxy + sx + 1], s);
+    for (int g0 = m0; g0 < m1; g0 += 8) {
+        const float fend = (float)min(g0 + 8, m1);
+        float part = 0.0f;
+        for (float fm = (float)g0; fm < fend; fm += 1.0f) {
+            const Cell s = cell_of(fmaf(fm, mr.st[0], mr.qs[0]), fmaf(fm, mr.st[1], mr.qs[1]),
+                                   fmaf(fm, mr.st[2], mr.qs[2]), bd);
+            const float* p = x + gindex(n, (int)s.i[0], (int)s.i[1], (int)s.i[2]);
+            part += tri(p[0], p[1], p[sx], p[sx + 1], p[sxy], p[sxy + 1], p[sxy + sx], p[sxy + sx + 1], s);
+        }
+        acc += (double)part;
     }
     return acc;
 }
@@ -382,7 +406,7 @@ __device__ __forceinline__ void scatter8(T* p, size_t sx, size_t sxy, const Cell
 // their LDS atomics do not collide on the same voxels.
 template <typename T>
 __device__ __forceinline__ void scatter_lds(const March& mr, int m0, int m1, const BrickRec& b,
-                                            T* brick, const float nm1[3], float v, bool skew)
+                                            T* brick, const Bounds& bd, float v, bool skew)
 {
     const float dx = (float)b.dim[0], dxy = (float)(b.dim[0] * b.dim[1]);
     const int sx = b.dim[0], sxy = b.dim[0] * b.dim[1];
@@ -393,7 +417,7 @@ __device__ __forceinline__ void scatter_lds(const March& mr, int m0, int m1, con
     for (int k = 0; k < cnt; ++k) {
         const float fm = (float)m;
         const Cell s = cell_of(fmaf(fm, mr.st[0], mr.qs[0]), fmaf(fm, mr.st[1], mr.qs[1]),
-                               fmaf(fm, mr.st[2], mr.qs[2]), nm1);
+                               fmaf(fm, mr.st[2], mr.qs[2]), bd);
         const float fi = fmaf(s.i[2], dxy, fmaf(s.i[1], dx, s.i[0])) - b.base;
         const int i0 = (int)clampf(fi, 0.0f, maxi);
         scatter8(brick + i0, (size_t)sx, (size_t)sxy, s, v, [](T* q, float a) { atomicAdd(q, (T)a); });
@@ -403,13 +427,13 @@ __device__ __forceinline__ void scatter_lds(const March& mr, int m0, int m1, con
 }
 
 __device__ __forceinline__ void scatter_global(const March& mr, int m0, int m1, const int n[3],
-                                               double* __restrict__ x, const float nm1[3], float v)
+                                               double* __restrict__ x, const Bounds& bd, float v)
 {
     const size_t sx = (size_t)n[0], sxy = (size_t)n[0] * n[1];
     for (int m = m0; m < m1; ++m) {
         const float fm = (float)m;
         const Cell s = cell_of(fmaf(fm, mr.st[0], mr.qs[0]), fmaf(fm, mr.st[1], mr.qs[1]),
-                               fmaf(fm, mr.st[2], mr.qs[2]), nm1);
+                               fmaf(fm, mr.st[2], mr.qs[2]), bd);
         double* p = x + gindex(n, (int)s.i[0], (int)s.i[1], (int)s.i[2]);
         scatter8(p, sx, sxy, s, v, [](double* q, float a) { unsafeAtomicAdd(q, (double)a); });
     }
@@ -490,7 +514,7 @@ __device__ void march_tile(const CamDev& c, int tile, const float* __restrict__ 
 {
     const Smem m = smem_of(smem, c);
     const TileRec t = c.tiles[tile];
-    const float nm1[3] = {(float)(c.n[0] - 1), (float)(c.n[1] - 1), (float)(c.n[2] - 1)};
+    const Bounds bd = bounds_of(c.n);
 
     // per-item words: forward sums start at 0, the adjoint reads y once
     for (int item = threadIdx.x; item < c.items_per_split; item += kThreads) {
@@ -534,17 +558,17 @@ __device__ void march_tile(const CamDev& c, int tile, const float* __restrict__ 
             if (m0 >= m1) continue;
             const March mr = march_of(r);
             if (!kAdj) {
-                const double s = b.lds ? gather_lds(mr, m0, m1, b, reinterpret_cast<const float*>(m.brick), nm1)
-                                       : gather_global(mr, m0, m1, c.n, in, nm1);
+                const double s = b.lds ? gather_lds(mr, m0, m1, b, reinterpret_cast<const float*>(m.brick), bd)
+                                       : gather_global(mr, m0, m1, c.n, in, bd);
                 atomicAdd(&m.item[item], s * (double)r.w);
             } else {
                 const float v = (float)m.item[item] * r.w;
                 if (!b.lds)
-                    scatter_global(mr, m0, m1, c.n, xacc, nm1, v);
+                    scatter_global(mr, m0, m1, c.n, xacc, bd, v);
                 else if (c.adj_f32)
-                    scatter_lds(mr, m0, m1, b, reinterpret_cast<float*>(m.brick), nm1, v, c.skew);
+                    scatter_lds(mr, m0, m1, b, reinterpret_cast<float*>(m.brick), bd, v, c.skew);
                 else
-                    scatter_lds(mr, m0, m1, b, reinterpret_cast<double*>(m.brick), nm1, v, c.skew);
+                    scatter_lds(mr, m0, m1, b, reinterpret_cast<double*>(m.brick), bd, v, c.skew);
             }
         }
         if (kAdj && b.lds) {

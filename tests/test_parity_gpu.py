@@ -158,3 +158,30 @@ def test_gpu_adjoint_is_transpose_entrywise(ltm, kind):
     assert scale > 0 and np.count_nonzero(A) > 0.05 * A.size
     assert np.array_equal(A != 0, AT.T != 0)           # identical sparsity
     assert np.max(np.abs(A - AT.T)) <= 1e-6 * scale
+
+
+@pytest.mark.parametrize("which", ["thin_lens_32", "plenoptic_128", "differentiable_256", "batched"])
+def test_valid_ray_counts_match_oracle(orc, ltm, which):
+    # occlusion (FP64 aperture tests) and the box hit test decide the same
+    # rays on both sides: the counts are equal integers
+    if which == "thin_lens_32":
+        cfg = W.config_thin_lens()
+        cases = [(cfg["grid"], cfg["cameras"])]
+    elif which == "plenoptic_128":
+        cfg = W.config_plenoptic()
+        cases = [(cfg["grid"], cfg["cameras"])]
+    elif which == "differentiable_256":
+        cfg = W.config_differentiable()
+        cases = [(cfg["grid"], cfg["cameras"])]
+    else:
+        seen, cases = set(), []
+        for f in W.config_batched():
+            if f["grid"]["nx"] not in seen:
+                seen.add(f["grid"]["nx"])
+                cases.append((f["grid"], f["cameras"]))
+    for g, cams in cases:
+        plan = ltm.Plan(g, cams)
+        for k, c in enumerate(cams):
+            gpu, ref = plan.valid_rays(k), orc.count_valid_rays(g, c)
+            print(which, g["nx"], k, gpu, ref, flush=True)
+            assert gpu == ref
