@@ -95,7 +95,9 @@ typedef struct ltm_camera {
  * lenslet's pixels on adjacent lanes, set walks adjacent lanes across
  * lenslets; bit 1 stops lanes from starting their angular-sample loop at
  * different samples; bit 2 (adjoint) accumulates the brick in FP32 before the
- * FP64 flush; bit 3 (adjoint) staggers the lanes' walks along their rays.  Each workgroup
+ * FP64 flush; bit 3 (adjoint) staggers the lanes' walks along their rays;
+ * bit 4 (adjoint) merges consecutive samples of one trilinear cell in
+ * registers before the LDS atomics.  Each workgroup
  * marches its rays through consecutive slabs of chunk_mm camera depth,
  * staging the voxels the slab's rays touch in an LDS brick of at most
  * brick_floats floats (a slab whose brick does not fit uses global memory).
@@ -147,6 +149,13 @@ ltm_status ltm_plan_set_tiling(ltm_plan* plan, uint32_t direction, uint32_t came
  * the plan's workspace and synchronizes the stream. */
 ltm_status ltm_plan_valid_rays(ltm_plan* plan, uint32_t camera, uint64_t* rays, void* stream);
 
+/* View subsets (the paper's view-subset acceleration): from now on project,
+ * backproject and ltm_plan_valid_rays use only angular samples
+ * r = ru + rays_u * rv with r mod n_subsets == index, averaged over the
+ * subset -- the subset operator scaled by K/|S|.  n_subsets = 1 restores the
+ * full operator.  The setting belongs to the plan (not thread-safe). */
+ltm_status ltm_plan_set_ray_subset(ltm_plan* plan, uint32_t n_subsets, uint32_t index);
+
 /* y = A x: ray integrals of the trilinear interpolant of x, averaged over
  * each pixel's angular samples (measurement-formation section; radiance as a
  * line integral through the object, object-model section).  x: N floats,
@@ -176,7 +185,8 @@ typedef struct ltm_solver_params {
     uint32_t momentum;          /* 1: FISTA, 0: projected gradient */
     uint32_t gains;             /* 1: estimate g_c for c >= 2 */
     uint32_t psi_kind;
-    uint32_t reserved;
+    uint32_t n_subsets;         /* > 1: iteration n uses angular-sample subset n mod n_subsets
+                                   (view-subset acceleration); the majorizer uses all samples */
     double beta, delta, nu, c_r;
 } ltm_solver_params;
 

@@ -74,6 +74,10 @@ def _lib_handle():
             lib.orc_clip.restype = ctypes.c_int
             lib.orc_project.argtypes = [gp, cp, ctypes.c_int, dp, dp, ctypes.c_int]
             lib.orc_backproject.argtypes = [gp, cp, ctypes.c_int, dp, dp, ctypes.c_int]
+            lib.orc_project_subset.argtypes = [gp, cp, ctypes.c_int, dp, dp, ctypes.c_int,
+                                               ctypes.c_int, ctypes.c_int]
+            lib.orc_backproject_subset.argtypes = [gp, cp, ctypes.c_int, dp, dp, ctypes.c_int,
+                                                   ctypes.c_int, ctypes.c_int]
             lib.orc_project_pixels.argtypes = [gp, cp, dp, ctypes.POINTER(ctypes.c_int64),
                                                ctypes.c_int64, dp, ctypes.c_int]
             lib.orc_pixel.argtypes = [gp, cp, dp, ctypes.c_int, ctypes.c_int]
@@ -151,27 +155,31 @@ def count_valid_rays(g: dict, cam: dict, threads: int | None = None) -> int:
 # --------------------------------------------------------------------------
 # A and A^T
 # --------------------------------------------------------------------------
-def project(g: dict, cams, x, threads: int | None = None) -> np.ndarray:
-    """y = A x (FP64), cameras concatenated, each image (nv, nu) flattened."""
+def project(g: dict, cams, x, threads: int | None = None, subsets: int = 1,
+            subset: int = 0) -> np.ndarray:
+    """y = A x (FP64), cameras concatenated, each image (nv, nu) flattened.
+    With subsets > 1: the operator of angular-sample subset `subset` (every
+    subsets-th sample, mean over the subset)."""
     lib = _lib_handle()
     x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1))
     assert x.size == n_voxels(g)
     y = np.zeros(n_meas(cams))
     gg = _grid(g)
-    lib.orc_project(ctypes.byref(gg), _cams(cams), len(cams), _dptr(x), _dptr(y),
-                    threads or default_threads())
+    lib.orc_project_subset(ctypes.byref(gg), _cams(cams), len(cams), _dptr(x), _dptr(y),
+                           subsets, subset, threads or default_threads())
     return y
 
 
-def backproject(g: dict, cams, y, threads: int | None = None) -> np.ndarray:
-    """x = A^T y (FP64), flattened (nz, ny, nx)."""
+def backproject(g: dict, cams, y, threads: int | None = None, subsets: int = 1,
+                subset: int = 0) -> np.ndarray:
+    """x = A^T y (FP64), flattened (nz, ny, nx); subsets as in project()."""
     lib = _lib_handle()
     y = np.ascontiguousarray(np.asarray(y, dtype=np.float64).reshape(-1))
     assert y.size == n_meas(cams)
     x = np.zeros(n_voxels(g))
     gg = _grid(g)
-    lib.orc_backproject(ctypes.byref(gg), _cams(cams), len(cams), _dptr(y), _dptr(x),
-                        threads or default_threads())
+    lib.orc_backproject_subset(ctypes.byref(gg), _cams(cams), len(cams), _dptr(y), _dptr(x),
+                               subsets, subset, threads or default_threads())
     return x
 
 
@@ -263,10 +271,13 @@ class Solver:
 
     def __init__(self, g, cams, ys, ws=None, beta=0.0, psi_kind=PSI_QUADRATIC, delta=1.0,
                  nu=0.0, c_r=36.0, momentum=True, gains=False, x0=None, threads=None,
-                 ops=None):
+                 ops=None, subsets=1):
         """ops: optional list of (forward, adjoint) callables, one per camera,
         replacing the camera operators (used to pin the algorithm on explicit
-        matrices)."""
+        matrices).  subsets > 1: the paper's view-subset acceleration --
+        iteration n uses angular-sample subset n mod subsets, each with its
+        (K/|S|)-scaled operator, while the majorizer uses all samples."""
+        self.subsets = subsets
         self.g, self.cams = g, list(cams)
         self.shape = (g["nz"], g["ny"], g["nx"])
         self.threads = threads
@@ -309,10 +320,18 @@ class Solver:
         y, w = self.ys[k], self.ws[k]
         return float(np.dot(y, w * p) / np.dot(y, w * y))
 
+    def _ops_now(self):
+        if self.subsets <= 1:
+            return self.ops
+        sub = self.n % self.subsets
+        return [((lambda v, c=c: project(self.g, [c], v, self.threads, self.subsets, sub)),
+                 (lambda r, c=c: backproject(self.g, [c], r, self.threads, self.subsets, sub)))
+                for c in self.cams]
+
     def step(self):
         grad = np.zeros_like(self.z)
         num = den = 0.0
-        for k, ((fwd, adj), y, w) in enumerate(zip(self.ops, self.ys, self.ws)):
+        for k, ((fwd, adj), y, w) in enumerate(zip(self._ops_now(), self.ys, self.ws)):
             p = fwd(self.z)
             if self.gains:
                 self.gamma[k] = self._gain(k, p)

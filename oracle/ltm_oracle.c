@@ -196,18 +196,39 @@ static void ray_scatter(const orc_grid* g, double* x, const double O[3], const d
     }
 }
 
-/* y_i of one pixel of one camera: mean over its R angular samples. */
-double orc_pixel(const orc_grid* g, const orc_camera* c, const double* x, int iu, int iv)
+/* Angular-sample subsets (the paper's view-subset acceleration): subset
+ * `idx` of `nsub` holds the samples r = ru + Ru*rv with r mod nsub == idx
+ * (every nsub-th sample in lexicographic order).  Its operator is the mean
+ * over the subset, i.e. the paper's (K/|S|) A_S.  nsub <= 1 is the full set. */
+static int in_subset(int r, int nsub, int idx) { return nsub <= 1 || r % nsub == idx; }
+
+static int subset_size(int R, int nsub, int idx)
+{
+    if (nsub <= 1) return R;
+    int n = 0;
+    for (int r = 0; r < R; ++r) n += (r % nsub == idx);
+    return n;
+}
+
+static double pixel_subset(const orc_grid* g, const orc_camera* c, const double* x, int iu, int iv,
+                           int nsub, int idx)
 {
     const int R = c->ru * c->rv;
     double acc = 0.0;
     for (int rv = 0; rv < c->rv; ++rv)
         for (int ru = 0; ru < c->ru; ++ru) {
             double O[3], w[3];
+            if (!in_subset(ru + c->ru * rv, nsub, idx)) continue;
             if (!orc_trace(c, iu, iv, ru, rv, O, w)) continue;
             acc += ray_integral(g, x, O, w, c->samples);
         }
-    return acc / R;
+    return acc / subset_size(R, nsub, idx);
+}
+
+/* y_i of one pixel of one camera: mean over its R angular samples. */
+double orc_pixel(const orc_grid* g, const orc_camera* c, const double* x, int iu, int iv)
+{
+    return pixel_subset(g, c, x, iu, iv, 1, 0);
 }
 
 static void set_threads(int nthreads)
@@ -217,6 +238,23 @@ static void set_threads(int nthreads)
 #else
     (void)nthreads;
 #endif
+}
+
+/* y = A_S x for angular-sample subset idx of nsub (nsub <= 1: all samples). */
+void orc_project_subset(const orc_grid* g, const orc_camera* cams, int ncam, const double* x,
+                        double* y, int nsub, int idx, int nthreads)
+{
+    set_threads(nthreads);
+    int64_t off = 0;
+    for (int ci = 0; ci < ncam; ++ci) {
+        const orc_camera* c = &cams[ci];
+        const int64_t np = (int64_t)c->nu * c->nv;
+        double* yc = y + off;
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t p = 0; p < np; ++p)
+            yc[p] = pixel_subset(g, c, x, (int)(p % c->nu), (int)(p / c->nu), nsub, idx);
+        off += np;
+    }
 }
 
 /* y = A x for all cameras, y concatenated camera by camera, each (nv, nu). */
@@ -246,11 +284,11 @@ void orc_project_pixels(const orc_grid* g, const orc_camera* c, const double* x,
         out[k] = orc_pixel(g, c, x, (int)(pix[k] % c->nu), (int)(pix[k] / c->nu));
 }
 
-/* x = A^T y.  Each thread scatters into a private FP64 volume; the volumes
- * are then added in thread order, so the result depends only on the thread
- * count. */
-void orc_backproject(const orc_grid* g, const orc_camera* cams, int ncam,
-                     const double* y, double* x, int nthreads)
+/* x = A_S^T y (nsub <= 1: A^T y).  Each thread scatters into a private FP64
+ * volume; the volumes are then added in thread order, so the result depends
+ * only on the thread count. */
+void orc_backproject_subset(const orc_grid* g, const orc_camera* cams, int ncam,
+                            const double* y, double* x, int nsub, int idx, int nthreads)
 {
     set_threads(nthreads);
     const int64_t N = (int64_t)g->nx * g->ny * g->nz;
@@ -265,7 +303,7 @@ void orc_backproject(const orc_grid* g, const orc_camera* cams, int ncam,
     for (int ci = 0; ci < ncam; ++ci) {
         const orc_camera* c = &cams[ci];
         const int64_t np = (int64_t)c->nu * c->nv;
-        const int R = c->ru * c->rv;
+        const int ns = subset_size(c->ru * c->rv, nsub, idx);
         const double* yc = y + off;
 #pragma omp parallel
         {
@@ -281,8 +319,9 @@ void orc_backproject(const orc_grid* g, const orc_camera* cams, int ncam,
                 for (int rv = 0; rv < c->rv; ++rv)
                     for (int ru = 0; ru < c->ru; ++ru) {
                         double O[3], w[3];
+                        if (!in_subset(ru + c->ru * rv, nsub, idx)) continue;
                         if (!orc_trace(c, iu, iv, ru, rv, O, w)) continue;
-                        ray_scatter(g, xt, O, w, c->samples, yc[p] / R);
+                        ray_scatter(g, xt, O, w, c->samples, yc[p] / ns);
                     }
             }
         }
@@ -293,6 +332,12 @@ void orc_backproject(const orc_grid* g, const orc_camera* cams, int ncam,
         for (int64_t j = 0; j < N; ++j) x[j] += xt[j];
     }
     free(priv);
+}
+
+void orc_backproject(const orc_grid* g, const orc_camera* cams, int ncam,
+                     const double* y, double* x, int nthreads)
+{
+    orc_backproject_subset(g, cams, ncam, y, x, 1, 0, nthreads);
 }
 
 /* Number of rays (over all pixels and angular samples) that are unoccluded

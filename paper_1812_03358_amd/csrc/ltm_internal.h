@@ -60,6 +60,8 @@ struct CamDev {
     int rotate;           // lanes start their aperture-sample loop at lane mod R
     int adj_f32;          // adjoint: FP32 LDS brick (flushed into the FP64 accumulator)
     int skew;             // adjoint: lanes start their sample walk at staggered offsets
+    int merge;            // adjoint: merge consecutive samples of one cell in registers
+    int sub_n, sub_i;     // angular-sample subset: keep r with r mod sub_n == sub_i
     int items, items_per_split, tiles_u, tiles_v, n_tiles;
     int brick_cap;        // LDS brick capacity in voxels (FP32 forward, FP64 adjoint)
     int max_chunks;
@@ -100,6 +102,7 @@ struct ltm_plan {
     uint64_t ws_bytes = 0;
     uint64_t counter_off = 0;   // 256-byte scratch word for ltm_plan_valid_rays
     uint64_t accum_off = 0;     // N doubles: FP64 accumulator of the adjoint
+    uint32_t sub_n = 1, sub_i = 0;   // current angular-sample subset
     char* ws = nullptr;
     bool bound = false;
 };

@@ -105,7 +105,7 @@ ltm_status check_tiling(const ltm_camera& c, const ltm_tiling& t)
         return fail(LTM_ERR_INVALID, "tiling sizes must be positive");
     if (c.kind == LTM_SINGLE_LENS && (t.block_u == 0 || t.block_v == 0))
         return fail(LTM_ERR_INVALID, "single-lens tiling needs block sizes");
-    if (t.order > 15) return fail(LTM_ERR_INVALID, "tiling order flags must be 0..15");
+    if (t.order > 31) return fail(LTM_ERR_INVALID, "tiling order flags must be 0..31");
     if (t.brick_floats > (uint32_t)kMaxBrickFloats)
         return fail(LTM_ERR_INVALID, "brick larger than 64 KiB of LDS");
     if (!(t.chunk_mm > 0) || !std::isfinite(t.chunk_mm))
@@ -238,6 +238,7 @@ void apply_tiling(const ltm_grid& g, const ltm_camera& c, const ltm_tiling& t, C
     d.rotate = (t.order & 2) ? 0 : 1;
     d.adj_f32 = (t.order & 4) ? 1 : 0;
     d.skew = (t.order & 8) ? 1 : 0;
+    d.merge = (t.order & 16) ? 1 : 0;
     d.splits = (int)t.splits;
     d.items = d.tile_u * d.tile_v * d.ku * d.kv;
     d.items_per_split = (d.items + d.splits - 1) / d.splits;
@@ -295,6 +296,18 @@ CamDev bound_dev(const ltm_plan* p, const CamHost& c, int dir)
     int nt, mc;
     apply_tiling(p->grid, c.desc, c.tiling[dir], d, nt, mc);
     if (dir == LTM_ADJOINT && !d.adj_f32) d.brick_cap /= 2;   // FP64 brick in the same LDS budget
+    if (p->sub_n > 1) {
+        // mean over the subset's samples: the view-subset operator (K/|S|) A_S
+        const int R = d.ru * d.rv;
+        int ns = 0;
+        for (int r = 0; r < R; ++r) ns += (r % (int)p->sub_n == (int)p->sub_i);
+        d.sub_n = (int)p->sub_n;
+        d.sub_i = (int)p->sub_i;
+        d.invR = ns > 0 ? (float)(1.0 / ns) : 0.0f;
+    } else {
+        d.sub_n = 1;
+        d.sub_i = 0;
+    }
     d.tiles = reinterpret_cast<const TileRec*>(p->ws + c.tiles_off[dir]);
     d.bricks = reinterpret_cast<const BrickRec*>(p->ws + c.bricks_off[dir]);
     d.y_off = c.y_off;
@@ -416,6 +429,16 @@ ltm_status ltm_plan_valid_rays(ltm_plan* p, uint32_t cam, uint64_t* rays, void* 
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "count rays");
     *rays = h;
+    return LTM_OK;
+}
+
+ltm_status ltm_plan_set_ray_subset(ltm_plan* p, uint32_t n_subsets, uint32_t index)
+{
+    if (!p) return fail(LTM_ERR_INVALID, "null plan");
+    if (n_subsets == 0 || n_subsets > (uint32_t)kMaxRays || (n_subsets > 1 && index >= n_subsets))
+        return fail(LTM_ERR_INVALID, "need 1 <= n_subsets <= 64 and index < n_subsets");
+    p->sub_n = n_subsets;
+    p->sub_i = n_subsets > 1 ? index : 0;
     return LTM_OK;
 }
 

@@ -63,6 +63,7 @@ __device__ __forceinline__ bool make_ray(const CamDev& c, int iu, int iv, int ru
     if ((long long)a * a * c.rv * c.rv + (long long)b * b * c.ru * c.ru >
         (long long)c.ru * c.ru * c.rv * c.rv)
         return false;
+    if (c.sub_n > 1 && (ru + c.ru * rv) % c.sub_n != c.sub_i) return false;
     const float gs = (float)a / (float)c.ru;
     const float gt = (float)b / (float)c.rv;
     float cu = 0.0f, cv = 0.0f;
@@ -426,6 +427,54 @@ __device__ __forceinline__ void scatter_lds(const March& mr, int m0, int m1, con
     }
 }
 
+// As scatter_lds, but a lane keeps the 8 corner weights of its current cell
+// in registers while consecutive samples stay in that cell, and issues the
+// LDS atomics only when the cell changes (rays advance about half a voxel
+// per sample, so cells repeat).
+template <typename T>
+__device__ __forceinline__ void scatter_lds_merged(const March& mr, int m0, int m1, const BrickRec& b,
+                                                   T* brick, const Bounds& bd, float v, bool skew)
+{
+    const float dx = (float)b.dim[0], dxy = (float)(b.dim[0] * b.dim[1]);
+    const int sx = b.dim[0], sxy = b.dim[0] * b.dim[1];
+    const float maxi = (float)(b.dim[0] * b.dim[1] * b.dim[2] - 1 - (1 + sx + sxy));
+    const int cnt = m1 - m0;
+    int m = m0;
+    if (skew) m += (int)(((threadIdx.x & 63) * (unsigned)cnt) >> 6);
+    int cur = -1;
+    float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    auto flush = [&](int i0) {
+        T* p = brick + i0;
+        const int off[8] = {0, 1, sx, sx + 1, sxy, sxy + 1, sxy + sx, sxy + sx + 1};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) atomicAdd(p + off[k], (T)a[k]);
+    };
+    for (int k = 0; k < cnt; ++k) {
+        const float fm = (float)m;
+        const Cell s = cell_of(fmaf(fm, mr.st[0], mr.qs[0]), fmaf(fm, mr.st[1], mr.qs[1]),
+                               fmaf(fm, mr.st[2], mr.qs[2]), bd);
+        const float fi = fmaf(s.i[2], dxy, fmaf(s.i[1], dx, s.i[0])) - b.base;
+        const int i0 = (int)clampf(fi, 0.0f, maxi);
+        const float gx = 1.0f - s.f[0], gy = 1.0f - s.f[1], gz = 1.0f - s.f[2];
+        const float z0 = v * gz, z1 = v * s.f[2];
+        const float a00 = gy * z0, a10 = s.f[1] * z0, a01 = gy * z1, a11 = s.f[1] * z1;
+        const float w[8] = {gx * a00, s.f[0] * a00, gx * a10, s.f[0] * a10,
+                            gx * a01, s.f[0] * a01, gx * a11, s.f[0] * a11};
+        if (i0 != cur) {
+            if (cur >= 0) flush(cur);
+            cur = i0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) a[j] = w[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) a[j] += w[j];
+        }
+        ++m;
+        m = m == m1 ? m0 : m;
+    }
+    if (cur >= 0) flush(cur);
+}
+
 __device__ __forceinline__ void scatter_global(const March& mr, int m0, int m1, const int n[3],
                                                double* __restrict__ x, const Bounds& bd, float v)
 {
@@ -565,6 +614,10 @@ __device__ void march_tile(const CamDev& c, int tile, const float* __restrict__ 
                 const float v = (float)m.item[item] * r.w;
                 if (!b.lds)
                     scatter_global(mr, m0, m1, c.n, xacc, bd, v);
+                else if (c.merge && c.adj_f32)
+                    scatter_lds_merged(mr, m0, m1, b, reinterpret_cast<float*>(m.brick), bd, v, c.skew);
+                else if (c.merge)
+                    scatter_lds_merged(mr, m0, m1, b, reinterpret_cast<double*>(m.brick), bd, v, c.skew);
                 else if (c.adj_f32)
                     scatter_lds(mr, m0, m1, b, reinterpret_cast<float*>(m.brick), bd, v, c.skew);
                 else

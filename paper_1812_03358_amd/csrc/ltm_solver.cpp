@@ -43,6 +43,8 @@ Layout solver_layout(const ltm_plan* p)
 ltm_status iterate(ltm_solver* s, hipStream_t st)
 {
     SolverDev& d = s->d;
+    const uint32_t ns = s->prm.n_subsets > 1 ? s->prm.n_subsets : 1;
+    ltm_plan_set_ray_subset(s->plan, ns, ns > 1 ? s->iter % ns : 0);
     ltm_status e = ltm_project(s->plan, d.z, d.p, st);
     if (e != LTM_OK) return e;
     hipError_t h = solver_launch_reduce(d, d.p, st);
@@ -57,6 +59,8 @@ ltm_status iterate(ltm_solver* s, hipStream_t st)
     }
     h = solver_launch_update(d, (float)s->prm.nu, st);
     if (h != hipSuccess) return hip_fail(h, "solver update");
+    ltm_plan_set_ray_subset(s->plan, 1, 0);
+    ++s->iter;
     return LTM_OK;
 }
 
@@ -83,6 +87,7 @@ ltm_status ltm_solver_create(ltm_plan* plan, const ltm_solver_params* prm, const
     if (!plan || !prm || !y) return fail(LTM_ERR_INVALID, "null argument");
     if (!plan->bound) return fail(LTM_ERR_WORKSPACE, "plan has no bound workspace");
     if (prm->psi_kind > LTM_PSI_HYPERBOLA) return fail(LTM_ERR_INVALID, "unknown potential");
+    if (prm->n_subsets > 64) return fail(LTM_ERR_INVALID, "at most 64 view subsets");
     if (!(prm->beta >= 0.0) || !(prm->nu >= 0.0) || !(prm->c_r >= 0.0) || !std::isfinite(prm->beta) ||
         !std::isfinite(prm->nu) || !std::isfinite(prm->c_r))
         return fail(LTM_ERR_INVALID, "beta, nu and c_R must be finite and nonnegative");
@@ -96,6 +101,7 @@ ltm_status ltm_solver_create(ltm_plan* plan, const ltm_solver_params* prm, const
         return fail(LTM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
     ltm_solver* s = new (std::nothrow) ltm_solver();
     if (!s) return fail(LTM_ERR_INVALID, "out of host memory");
+    ltm_plan_set_ray_subset(plan, 1, 0);   // the majorizer uses every angular sample
     s->plan = plan;
     s->prm = *prm;
     char* b = static_cast<char*>(ws);
@@ -180,6 +186,7 @@ ltm_status ltm_solver_reset(ltm_solver* s, const float* x0, void* stream)
     }
     if (h == hipSuccess) h = solver_launch_reset(s->d, st);
     if (h != hipSuccess) return hip_fail(h, "solver reset");
+    s->iter = 0;
     return LTM_OK;
 }
 
@@ -221,6 +228,7 @@ ltm_status ltm_solver_residual_x(ltm_solver* s, double* rho, void* stream)
 {
     if (!s || !rho) return fail(LTM_ERR_INVALID, "null argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    ltm_plan_set_ray_subset(s->plan, 1, 0);
     ltm_status e = ltm_project(s->plan, s->d.x, s->d.p, st);
     if (e != LTM_OK) return e;
     hipError_t h = solver_launch_reduce(s->d, s->d.p, st);
@@ -266,6 +274,7 @@ ltm_status ltm_solver_load(ltm_solver* s, const float* x, const float* z, double
     if (h != hipSuccess) return hip_fail(h, "load solver state");
     sc[SC_T] = t;
     sc[SC_ITER] = (double)iterations;
+    s->iter = iterations;
     sc[SC_MOM] = 0.0;
     if (gains)
         for (int c = 0; c < nc; ++c) sc[SC_CAM + SC_GAMMA * nc + c] = gains[c];

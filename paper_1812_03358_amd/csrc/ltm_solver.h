@@ -45,4 +45,5 @@ struct ltm_solver {
     ltm_solver_params prm{};
     ltm::SolverDev d{};
     std::vector<uint64_t> cam_off;
+    uint32_t iter = 0;        // host count of iterations (selects the view subset)
 };

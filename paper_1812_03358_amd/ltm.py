@@ -62,7 +62,7 @@ class Tiling(ctypes.Structure):
 
 class SolverParams(ctypes.Structure):
     _fields_ = [("momentum", ctypes.c_uint32), ("gains", ctypes.c_uint32),
-                ("psi_kind", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("psi_kind", ctypes.c_uint32), ("n_subsets", ctypes.c_uint32),
                 ("beta", ctypes.c_double), ("delta", ctypes.c_double),
                 ("nu", ctypes.c_double), ("c_r", ctypes.c_double)]
 
@@ -89,6 +89,7 @@ _SIGS = {
     "ltm_plan_get_tiling": (ctypes.c_int, [_VP, _U32, _U32, ctypes.POINTER(Tiling)]),
     "ltm_plan_set_tiling": (ctypes.c_int, [_VP, _U32, _U32, ctypes.POINTER(Tiling)]),
     "ltm_plan_valid_rays": (ctypes.c_int, [_VP, _U32, ctypes.POINTER(_U64), _VP]),
+    "ltm_plan_set_ray_subset": (ctypes.c_int, [_VP, _U32, _U32]),
     "ltm_project": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "ltm_backproject": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "ltm_solver_workspace_bytes": (ctypes.c_int, [_VP, ctypes.POINTER(_U64)]),
@@ -255,6 +256,11 @@ class Plan:
         if rebind:
             self.bind(stream)
 
+    def set_ray_subset(self, n_subsets: int = 1, index: int = 0):
+        """Restrict project/backproject to angular-sample subset `index` of
+        `n_subsets` (mean over the subset); (1, 0) restores the full operator."""
+        _check(lib().ltm_plan_set_ray_subset(self._h, n_subsets, index))
+
     def valid_rays(self, camera: int = 0, stream=None) -> int:
         n = ctypes.c_uint64()
         _check(lib().ltm_plan_valid_rays(self._h, camera, ctypes.byref(n), _stream(stream)))
@@ -283,14 +289,14 @@ class Solver:
 
     def __init__(self, plan: Plan, y: torch.Tensor, w: torch.Tensor | None = None, *,
                  beta=0.0, delta=1.0, nu=0.0, c_r=36.0, psi_kind=PSI_QUADRATIC,
-                 momentum=True, gains=False, stream=None):
+                 momentum=True, gains=False, subsets=1, stream=None):
         self.plan = plan
         self.y = y
         self.w = w
         b = ctypes.c_uint64()
         _check(lib().ltm_solver_workspace_bytes(plan.handle, ctypes.byref(b)))
         self.workspace = torch.empty(b.value, dtype=torch.uint8, device=y.device)
-        self.params = SolverParams(int(momentum), int(gains), int(psi_kind), 0,
+        self.params = SolverParams(int(momentum), int(gains), int(psi_kind), int(subsets),
                                    float(beta), float(delta), float(nu), float(c_r))
         h = ctypes.c_void_p()
         _check(lib().ltm_solver_create(plan.handle, ctypes.byref(self.params),

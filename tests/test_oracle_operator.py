@@ -101,3 +101,35 @@ def test_flame_volume_statistics():
     assert abs(cx - 15.5) < 3 and abs(cz - 15.5) < 3
     assert np.array_equal(v, W.flame(32, seed=2))           # seeded
     assert not np.array_equal(v, W.flame(32, seed=3))
+
+
+@pytest.mark.parametrize("nsub", [2, 3, 4])
+def test_view_subsets_partition_the_operator(orc, nsub):
+    # the paper's view subsets: every nsub-th angular sample; the subset
+    # operator is the mean over its samples, so sum_n |S_n|/K A_Sn = A
+    g = W.grid((9, 10, 11), 12.0)
+    cam = W.plenoptic_camera(32, 2, (2, 2), 19, phi_deg=25.0)
+    x = W.uniform_random(9 * 10 * 11, seed=12).astype(np.float64)
+    y = W.uniform_random(32 * 32, seed=13).astype(np.float64)
+    R = 4
+    sizes = [len([r for r in range(R) if r % nsub == n]) for n in range(nsub)]
+    full = orc.project(g, [cam], x)
+    acc = sum(sizes[n] / R * orc.project(g, [cam], x, subsets=nsub, subset=n) for n in range(nsub))
+    assert np.max(np.abs(acc - full)) <= 1e-13 * np.max(full)
+    accb = sum(sizes[n] / R * orc.backproject(g, [cam], y, subsets=nsub, subset=n) for n in range(nsub))
+    assert np.max(np.abs(accb - orc.backproject(g, [cam], y))) <= 1e-12 * np.max(np.abs(accb))
+    for n in range(nsub):
+        Ax = orc.project(g, [cam], x, subsets=nsub, subset=n)
+        Aty = orc.backproject(g, [cam], y, subsets=nsub, subset=n)
+        assert abs(np.dot(Ax, y) - np.dot(x, Aty)) <= 1e-13 * np.linalg.norm(Ax) * np.linalg.norm(y)
+
+
+def test_view_subset_solver_decreases_residual(orc):
+    g = W.grid(8, 20.0)
+    cams = [W.plenoptic_camera(32, 2, (2, 2), 17, phi_deg=p) for p in (0.0, 90.0)]
+    xt = W.flame(8, seed=4).astype(np.float64)
+    y = orc.project(g, cams, xt.reshape(-1))
+    s = orc.Solver(g, cams, [y[:1024], y[1024:]], subsets=2, momentum=False)
+    r0 = s.residual(s.x)
+    s.run(10)
+    assert s.residual(s.x) < 0.5 * r0

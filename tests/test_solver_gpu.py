@@ -165,3 +165,41 @@ def test_plenoptic_128_fista_5_iterations(orc, ltm):
     print("rel", rel_l2(x, ref.x), "rho", rho, ref.rho, flush=True)
     assert rel_l2(x, ref.x) < 1e-4
     assert abs(rho - ref.rho) < 1e-6
+
+
+@pytest.mark.parametrize("nsub", [2, 4])
+def test_view_subset_operators_match_oracle(orc, ltm, nsub):
+    g = W.grid((20, 24, 18), 6.0)
+    cams = [W.plenoptic_camera(96, 6, (2, 2), 37, phi_deg=30.0)]
+    x = W.flame(24, seed=7)[:18, :24, :20]
+    y = W.uniform_random(96 * 96, seed=32)
+    plan = ltm.Plan(g, cams)
+    xd = torch.from_numpy(np.ascontiguousarray(x).reshape(-1)).cuda()
+    yd = torch.from_numpy(y).cuda()
+    for n in range(nsub):
+        plan.set_ray_subset(nsub, n)
+        Ax = plan.project(xd).cpu().numpy()
+        Aty = plan.backproject(yd).cpu().numpy()
+        assert rel_l2(Ax, orc.project(g, cams, x.astype(np.float64).reshape(-1), subsets=nsub,
+                                      subset=n)) < 1e-5
+        assert rel_l2(Aty, orc.backproject(g, cams, y.astype(np.float64), subsets=nsub,
+                                           subset=n)) < 1e-5
+    plan.set_ray_subset(1, 0)
+    assert rel_l2(plan.project(xd).cpu().numpy(),
+                  orc.project(g, cams, x.astype(np.float64).reshape(-1))) < 1e-5
+
+
+def test_view_subset_fista_matches_oracle(orc, ltm):
+    g = W.grid((20, 24, 18), 6.0)
+    cams = [W.plenoptic_camera(96, 6, (2, 2), 37, phi_deg=p) for p in (0.0, 90.0)]
+    xt = W.flame(24, seed=7)[:18, :24, :20].astype(np.float64)
+    y = orc.project(g, cams, xt.reshape(-1))
+    ref = orc.Solver(g, cams, [y[:96 * 96], y[96 * 96:]], momentum=True, subsets=2)
+    ref.run(8)
+    plan, s = _gpu_solver(ltm, g, cams, [y], momentum=True, subsets=2)
+    s.step(8)
+    x = s.x().cpu().numpy()
+    rho, _ = s.residual()
+    print("rel", rel_l2(x, ref.x), "rho", rho, ref.rho, flush=True)
+    assert rel_l2(x, ref.x) < 1e-4
+    assert abs(rho - ref.rho) < 1e-6
