@@ -245,3 +245,32 @@ def config_warm_start():
     return dict(name="warm_start_128", grid=grid(128, 1.25),
                 cameras=[plenoptic_camera(1024, 64, (2, 2), 256, phi)
                          for phi in (0.0, 90.0)])
+
+
+def config_three_camera(n: int = 100, det_pl: int = 2048, mla: int = 128, det_tl: int = 1024,
+                        samples: int = 200):
+    """One plenoptic camera head-on and two single-lens cameras at +-30 deg
+    (the paper's three-camera experiment), 100^3 at 1 mm; the single-lens
+    cameras read the light with unknown gains 0.8 and 1.3, the plenoptic
+    camera keeps only its green Bayer pixels and one single-lens camera has a
+    damaged block of pixels (both through the weights W)."""
+    cams = [plenoptic_camera(det_pl, mla, (2, 2), samples, 0.0),
+            single_lens_camera(det_tl, (2, 2), samples, 30.0),
+            single_lens_camera(det_tl, (2, 2), samples, -30.0)]
+    return dict(name="three_camera_100", grid=grid(n, 100.0 / n), cameras=cams,
+                volume=lambda: flame(n, 5), gains=[1.0, 0.8, 1.3])
+
+
+def bayer_green_mask(nu: int, nv: int) -> np.ndarray:
+    """1 on the green sites of an RGGB mosaic ((u + v) odd), else 0."""
+    u = np.arange(nu)[None, :]
+    v = np.arange(nv)[:, None]
+    return (((u + v) % 2) == 1).astype(np.float32).reshape(-1)
+
+
+def damaged_mask(nu: int, nv: int, box=(0.6, 0.8, 0.1, 0.3)) -> np.ndarray:
+    """1 except a rectangular block (fractions u0, u1, v0, v1) set to 0."""
+    m = np.ones((nv, nu), np.float32)
+    u0, u1, v0, v1 = (int(box[0] * nu), int(box[1] * nu), int(box[2] * nv), int(box[3] * nv))
+    m[v0:v1, u0:u1] = 0.0
+    return m.reshape(-1)

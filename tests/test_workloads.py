@@ -70,3 +70,18 @@ def test_noise_recipes():
     # counts are integers after scaling by peak / max
     counts = yp.astype(np.float64) * 1000 / 2.0
     assert np.allclose(counts, np.round(counts), atol=1e-3)
+
+
+def test_weight_masks():
+    m = W.bayer_green_mask(6, 4).reshape(4, 6)
+    assert m.sum() == 12 and m[0, 1] == 1 and m[0, 0] == 0 and m[1, 0] == 1
+    d = W.damaged_mask(100, 50).reshape(50, 100)
+    assert (d == 0).sum() == 20 * 10 and d[5:15, 60:80].max() == 0 and d[0, 0] == 1
+
+
+def test_three_camera_config():
+    cfg = W.config_three_camera()
+    kinds = [c["kind"] for c in cfg["cameras"]]
+    assert kinds == [W.PLENOPTIC, W.SINGLE_LENS, W.SINGLE_LENS]
+    assert [c["phi_deg"] for c in cfg["cameras"]] == [0.0, 30.0, -30.0]
+    assert cfg["gains"][0] == 1.0
