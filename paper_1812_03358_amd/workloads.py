@@ -248,15 +248,15 @@ def config_warm_start():
 
 
 def config_three_camera(n: int = 100, det_pl: int = 2048, mla: int = 128, det_tl: int = 1024,
-                        samples: int = 200):
+                        rays=(8, 8), samples: int = 200):
     """One plenoptic camera head-on and two single-lens cameras at +-30 deg
-    (the paper's three-camera experiment), 100^3 at 1 mm; the single-lens
-    cameras read the light with unknown gains 0.8 and 1.3, the plenoptic
-    camera keeps only its green Bayer pixels and one single-lens camera has a
-    damaged block of pixels (both through the weights W)."""
-    cams = [plenoptic_camera(det_pl, mla, (2, 2), samples, 0.0),
-            single_lens_camera(det_tl, (2, 2), samples, 30.0),
-            single_lens_camera(det_tl, (2, 2), samples, -30.0)]
+    (the paper's three-camera experiment): 100^3 at 1 mm, an 8x8 angular grid
+    per camera, no subsets.  ``gains`` are the planted gains that divide each
+    camera's clean image (the first camera's is 1); per-pixel weights come
+    from ``bayer_green_mask`` and ``damaged_mask``."""
+    cams = [plenoptic_camera(det_pl, mla, rays, samples, 0.0),
+            single_lens_camera(det_tl, rays, samples, 30.0),
+            single_lens_camera(det_tl, rays, samples, -30.0)]
     return dict(name="three_camera_100", grid=grid(n, 100.0 / n), cameras=cams,
                 volume=lambda: flame(n, 5), gains=[1.0, 0.8, 1.3])
 

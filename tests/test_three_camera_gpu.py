@@ -21,7 +21,7 @@ def rel_l2(a, b):
 
 def test_three_camera_gains_and_weights(orc):
     from paper_1812_03358_amd import ltm
-    cfg = W.config_three_camera(n=24, det_pl=256, mla=16, det_tl=128, samples=48)
+    cfg = W.config_three_camera(n=24, det_pl=256, mla=16, det_tl=128, rays=(2, 2), samples=48)
     g, cams = cfg["grid"], cfg["cameras"]
     xt = cfg["volume"]().astype(np.float64)
     ys = [orc.project(g, [c], xt.reshape(-1)) / gain for c, gain in zip(cams, cfg["gains"])]
