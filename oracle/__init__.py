@@ -57,7 +57,8 @@ class Camera(ctypes.Structure):
                 ("d_det", ctypes.c_double),
                 ("d_mla", ctypes.c_double), ("d_mla_det", ctypes.c_double),
                 ("f_mla", ctypes.c_double), ("r_mla", ctypes.c_double),
-                ("axes", ctypes.c_double * 9), ("lens", ctypes.c_double * 3)]
+                ("axes", ctypes.c_double * 9), ("lens", ctypes.c_double * 3),
+                ("f_hex", ctypes.c_double * 3)]
 
 
 def _lib_handle():
@@ -70,6 +71,13 @@ def _lib_handle():
             lib.orc_trace.argtypes = [cp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, dp, dp]
             lib.orc_trace.restype = ctypes.c_int
+            lib.orc_trace_path.argtypes = [cp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_int, dp, dp]
+            lib.orc_trace_path.restype = ctypes.c_int
+            ip = ctypes.POINTER(ctypes.c_int)
+            lib.orc_hex_lenslet.argtypes = [cp, ctypes.c_int, ctypes.c_int, dp, dp, ip]
+            lib.orc_paths.argtypes = [cp]
+            lib.orc_paths.restype = ctypes.c_int
             lib.orc_clip.argtypes = [gp, dp, dp, dp]
             lib.orc_clip.restype = ctypes.c_int
             lib.orc_project.argtypes = [gp, cp, ctypes.c_int, dp, dp, ctypes.c_int]
@@ -104,7 +112,8 @@ def _cams(cams) -> ctypes.Array:
                         c["rays_u"], c["rays_v"], c["samples"], c["pixel_pitch"],
                         c["f_main"], c["r_main"], c["d_det"], c["d_mla"], c["d_mla_det"],
                         c["f_mla"], c["r_mla"], (ctypes.c_double * 9)(*c["axes"]),
-                        (ctypes.c_double * 3)(*c["lens_center"]))
+                        (ctypes.c_double * 3)(*c["lens_center"]),
+                        (ctypes.c_double * 3)(*c.get("f_hex", (0.0, 0.0, 0.0))))
     return arr
 
 
@@ -132,6 +141,28 @@ def trace(cam: dict, iu: int, iv: int, ru: int, rv: int):
     c = _cams([cam])
     v = lib.orc_trace(c, iu, iv, ru, rv, _dptr(O), _dptr(w))
     return bool(v), O, w
+
+
+def trace_path(cam: dict, iu: int, iv: int, path: int, ru: int, rv: int):
+    """Like ``trace`` for light path ``path`` (the lenslet index j*mu + i of a
+    hexagonal array; 0 for the other kinds)."""
+    lib = _lib_handle()
+    O = np.zeros(3)
+    w = np.zeros(3)
+    v = lib.orc_trace_path(_cams([cam]), iu, iv, path, ru, rv, _dptr(O), _dptr(w))
+    return bool(v), O, w
+
+
+def hex_lenslet(cam: dict, i: int, j: int):
+    """(s, t, type) of lenslet (i, j) of a hexagonal array, mm."""
+    lib = _lib_handle()
+    cs, ct, ty = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+    lib.orc_hex_lenslet(_cams([cam]), i, j, ctypes.byref(cs), ctypes.byref(ct), ctypes.byref(ty))
+    return cs.value, ct.value, ty.value
+
+
+def n_paths(cam: dict) -> int:
+    return int(_lib_handle().orc_paths(_cams([cam])))
 
 
 def clip(g: dict, O, w):

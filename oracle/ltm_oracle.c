@@ -11,6 +11,12 @@
  *                   transformations: propagation s' = s + d u and thin-lens
  *                   refraction u' = u - (s - s0)/f, composed detector -> scene
  *                   (single-lens and plenoptic camera models);
+ *   lenslets     -- square array, each pixel seeing only through the
+ *                   lenslet above it; or hexagonal array of three focal
+ *                   lengths (table of the simulated plenoptic camera), each
+ *                   pixel summing the light of every lenslet of the array
+ *                   (the sum over microlenses of the plenoptic-camera
+ *                   section), checked here by brute force over all lenslets;
  *   occlusion    -- a ray is kept only if it passes inside the lenslet
  *                   aperture and the main-lens aperture (occlusion masks of
  *                   the occlusion and plenoptic-camera sections; closed
@@ -42,7 +48,7 @@ typedef struct {
 } orc_grid;
 
 typedef struct {
-    int32_t kind;                 /* 0 single lens, 1 plenoptic */
+    int32_t kind;                 /* 0 single lens, 1 plenoptic, 2 hexagonal plenoptic */
     int32_t nu, nv;               /* detector pixels (u = s direction fastest) */
     int32_t mu, mv;               /* lenslets (plenoptic) */
     int32_t ru, rv;               /* angular samples per pixel: ru x rv grid */
@@ -54,7 +60,28 @@ typedef struct {
     double f_mla, r_mla;          /* lenslet focal length and radius */
     double axes[9];               /* e_s, e_t, e_z in world coordinates */
     double lens[3];               /* main-lens centre in world coordinates */
+    double f_hex[3];              /* hexagonal array: focal length of each lenslet type */
 } orc_camera;
+
+/* Hexagonal lenslet array: mu lenslets per row, mv rows, touching discs of
+ * radius r (pitch p = 2r, row spacing p sqrt(3)/2).  Rows whose distance
+ * from row mv/2 is odd are shifted by p/2 along s.  Lenslet (i, j) has
+ * hexagonal axial coordinates (q, r) with s/p = q + r/2 + const and r = j -
+ * mv/2; its type (q - r) mod 3 differs from each of its six neighbours'. */
+void orc_hex_lenslet(const orc_camera* c, int i, int j, double* cs, double* ct, int* type)
+{
+    const double p = 2.0 * c->r_mla, h = p * sqrt(3.0) / 2.0;
+    const int r = j - c->mv / 2;
+    const int odd = r & 1;
+    *cs = (i - 0.5 * (c->mu - 1) + 0.5 * odd) * p;
+    *ct = (j - 0.5 * (c->mv - 1)) * h;
+    const int q2 = 2 * i + odd - r;                /* 2q, always even */
+    *type = (((q2 / 2 - r) % 3) + 3) % 3;
+}
+
+/* Number of light paths per (pixel, angular sample): one lenslet (or the
+ * lens) for kinds 0 and 1, every lenslet of the array for kind 2. */
+int orc_paths(const orc_camera* c) { return c->kind == 2 ? c->mu * c->mv : 1; }
 
 /* ------------------------------------------------------------------------ */
 /* Ray optics.  A ray is (s,u,t,v) with u = ds/dz.  Starting on the detector
@@ -63,8 +90,8 @@ typedef struct {
  * refract.  The result is the ray leaving the main lens (z = 0) towards the
  * scene, returned in world coordinates as origin O and direction w with
  * w . e_z = 1 (so the ray parameter is the camera depth z).              */
-int orc_trace(const orc_camera* c, int iu, int iv, int ru, int rv,
-              double O[3], double w[3])
+int orc_trace_path(const orc_camera* c, int iu, int iv, int path, int ru, int rv,
+                   double O[3], double w[3])
 {
     const double gs = (2.0 * ru + 1.0) / c->ru - 1.0;   /* aperture grid cell centre */
     const double gt = (2.0 * rv + 1.0) / c->rv - 1.0;   /* in [-1, 1]               */
@@ -82,6 +109,22 @@ int orc_trace(const orc_camera* c, int iu, int iv, int ru, int rv,
         v2 = v - at / c->f_main;
         s0 = as;
         t0 = at;
+    } else if (c->kind == 2) {
+        /* angular sample on lenslet `path`, refracted by that lenslet's type */
+        double cs, ct;
+        int type;
+        orc_hex_lenslet(c, path % c->mu, path / c->mu, &cs, &ct, &type);
+        const double f = c->f_hex[type];
+        const double as = cs + c->r_mla * gs, at = ct + c->r_mla * gt;
+        const double u = (as - sd) / c->d_mla_det;
+        const double v = (at - td) / c->d_mla_det;
+        const double u1 = u - (as - cs) / f;
+        const double v1 = v - (at - ct) / f;
+        s0 = as + u1 * c->d_mla;
+        t0 = at + v1 * c->d_mla;
+        if (s0 * s0 + t0 * t0 > c->r_main * c->r_main) valid = 0;
+        u2 = u1 - s0 / c->f_main;
+        v2 = v1 - t0 / c->f_main;
     } else {
         const int ku = c->nu / c->mu, kv = c->nv / c->mv;
         const int lu = iu / ku, lv = iv / kv;             /* this pixel's lenslet */
@@ -107,6 +150,11 @@ int orc_trace(const orc_camera* c, int iu, int iv, int ru, int rv,
         w[a] = u2 * es[a] + v2 * et[a] + ez[a];
     }
     return valid;
+}
+
+int orc_trace(const orc_camera* c, int iu, int iv, int ru, int rv, double O[3], double w[3])
+{
+    return orc_trace_path(c, iu, iv, 0, ru, rv, O, w);
 }
 
 /* Segment of the ray inside the grid's box [-n dx/2, n dx/2]^3, restricted to
@@ -215,13 +263,14 @@ static double pixel_subset(const orc_grid* g, const orc_camera* c, const double*
 {
     const int R = c->ru * c->rv;
     double acc = 0.0;
-    for (int rv = 0; rv < c->rv; ++rv)
-        for (int ru = 0; ru < c->ru; ++ru) {
-            double O[3], w[3];
-            if (!in_subset(ru + c->ru * rv, nsub, idx)) continue;
-            if (!orc_trace(c, iu, iv, ru, rv, O, w)) continue;
-            acc += ray_integral(g, x, O, w, c->samples);
-        }
+    for (int path = 0; path < orc_paths(c); ++path)
+        for (int rv = 0; rv < c->rv; ++rv)
+            for (int ru = 0; ru < c->ru; ++ru) {
+                double O[3], w[3];
+                if (!in_subset(ru + c->ru * rv, nsub, idx)) continue;
+                if (!orc_trace_path(c, iu, iv, path, ru, rv, O, w)) continue;
+                acc += ray_integral(g, x, O, w, c->samples);
+            }
     return acc / subset_size(R, nsub, idx);
 }
 
@@ -316,13 +365,14 @@ void orc_backproject_subset(const orc_grid* g, const orc_camera* cams, int ncam,
             for (int64_t p = 0; p < np; ++p) {
                 if (yc[p] == 0.0) continue;
                 const int iu = (int)(p % c->nu), iv = (int)(p / c->nu);
-                for (int rv = 0; rv < c->rv; ++rv)
-                    for (int ru = 0; ru < c->ru; ++ru) {
-                        double O[3], w[3];
-                        if (!in_subset(ru + c->ru * rv, nsub, idx)) continue;
-                        if (!orc_trace(c, iu, iv, ru, rv, O, w)) continue;
-                        ray_scatter(g, xt, O, w, c->samples, yc[p] / ns);
-                    }
+                for (int path = 0; path < orc_paths(c); ++path)
+                    for (int rv = 0; rv < c->rv; ++rv)
+                        for (int ru = 0; ru < c->ru; ++ru) {
+                            double O[3], w[3];
+                            if (!in_subset(ru + c->ru * rv, nsub, idx)) continue;
+                            if (!orc_trace_path(c, iu, iv, path, ru, rv, O, w)) continue;
+                            ray_scatter(g, xt, O, w, c->samples, yc[p] / ns);
+                        }
             }
         }
         off += np;
@@ -349,11 +399,13 @@ int64_t orc_count_valid_rays(const orc_grid* g, const orc_camera* c, int nthread
     int64_t count = 0;
 #pragma omp parallel for reduction(+ : count) schedule(dynamic, 256)
     for (int64_t p = 0; p < np; ++p)
-        for (int rv = 0; rv < c->rv; ++rv)
-            for (int ru = 0; ru < c->ru; ++ru) {
-                double O[3], w[3], zr[2];
-                if (!orc_trace(c, (int)(p % c->nu), (int)(p / c->nu), ru, rv, O, w)) continue;
-                if (orc_clip(g, O, w, zr)) ++count;
-            }
+        for (int path = 0; path < orc_paths(c); ++path)
+            for (int rv = 0; rv < c->rv; ++rv)
+                for (int ru = 0; ru < c->ru; ++ru) {
+                    double O[3], w[3], zr[2];
+                    if (!orc_trace_path(c, (int)(p % c->nu), (int)(p / c->nu), path, ru, rv, O, w))
+                        continue;
+                    if (orc_clip(g, O, w, zr)) ++count;
+                }
     return count;
 }

@@ -27,6 +27,7 @@ import numpy as np
 
 SINGLE_LENS = 0
 PLENOPTIC = 1
+PLENOPTIC_HEX = 2
 
 # --------------------------------------------------------------------------
 # geometry constants (mm)
@@ -34,6 +35,8 @@ PLENOPTIC = 1
 TL_F, TL_R, TL_D, TL_PITCH = 30.0, 5.0, 31.3, 0.005
 PL_F, PL_R, PL_DMM, PL_DMD = 105.0, 4.5, 112.0, 2.2
 PL_FMU, PL_RMU, PL_PMU = 3.0, 0.1, 0.2
+PL_FHEX = (2.8, 3.0, 3.2)       # the three lenslet focal lengths of the table
+PL_HEX_PIXEL = 0.005            # 5 um pixels of the table
 
 
 def azimuth_axes(phi_deg: float):
@@ -85,6 +88,27 @@ def plenoptic_camera(det: int = 1024, mla: int = 64, rays=(2, 2), samples: int =
                rays_u=rays[0], rays_v=rays[1], samples=samples,
                pixel_pitch=PL_PMU / k, f_main=PL_F, r_main=PL_R, d_det=0.0,
                d_mla=PL_DMM, d_mla_det=PL_DMD, f_mla=PL_FMU, r_mla=PL_RMU)
+    return _place(cam, distance, phi_deg)
+
+
+def hex_plenoptic_camera(det: int = 2048, mla=None, rays=(2, 2), samples: int = 256,
+                         phi_deg: float = 0.0, distance: float | None = None,
+                         f_hex=PL_FHEX, r_main: float = PL_R) -> dict:
+    """Plenoptic camera of the paper's simulated plenoptic table as listed:
+    hexagonal array of touching 100 um lenslets of three focal lengths, 5 um
+    pixels, every pixel summing the light of all lenslets.  ``mla`` =
+    (lenslets per row, rows); the default covers the detector with one
+    lenslet to spare on each side."""
+    p = 2.0 * PL_RMU
+    if mla is None:
+        side = det * PL_HEX_PIXEL
+        mla = (int(math.ceil(side / p)) + 1, int(math.ceil(side / (p * math.sqrt(3) / 2))) + 1)
+    if distance is None:
+        distance = PL_F * PL_DMM / (PL_DMM - PL_F)
+    cam = dict(kind=PLENOPTIC_HEX, det_nu=det, det_nv=det, mla_nu=int(mla[0]), mla_nv=int(mla[1]),
+               rays_u=rays[0], rays_v=rays[1], samples=samples, pixel_pitch=PL_HEX_PIXEL,
+               f_main=PL_F, r_main=r_main, d_det=0.0, d_mla=PL_DMM, d_mla_det=PL_DMD,
+               f_mla=f_hex[1], r_mla=PL_RMU, f_hex=[float(f) for f in f_hex])
     return _place(cam, distance, phi_deg)
 
 
