@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LTM_ABI_VERSION 1u
+#define LTM_ABI_VERSION 2u
 
 typedef enum ltm_status {
     LTM_OK = 0,
@@ -48,7 +48,7 @@ typedef enum ltm_status {
     LTM_ERR_UNSUPPORTED = 5   /* valid request the library does not implement */
 } ltm_status;
 
-enum { LTM_SINGLE_LENS = 0u, LTM_PLENOPTIC = 1u };
+enum { LTM_SINGLE_LENS = 0u, LTM_PLENOPTIC = 1u, LTM_PLENOPTIC_HEX = 2u };
 enum { LTM_FORWARD = 0u, LTM_ADJOINT = 1u };
 
 /* Voxel grid centred at the world origin (object-model section: pillbox
@@ -64,20 +64,40 @@ typedef struct ltm_grid {
  *   single lens: the detector at depth -d_det;
  *   plenoptic:   a square microlens array at depth -d_mla (lenslets of
  *                radius r_mla, focal length f_mla, pitch det_nu/mla_nu
- *                pixels) and the detector d_mla_det behind it.
+ *                pixels) and the detector d_mla_det behind it;
+ *   hexagonal plenoptic (the simulated plenoptic table as listed): a
+ *                hexagonal array of mla_nu lenslets per row and mla_nv rows
+ *                of touching lenslets (pitch 2 r_mla, row spacing
+ *                sqrt(3) r_mla; rows at odd distance from row mla_nv/2
+ *                shifted by r_mla along s; lenslet (i, j) at
+ *                s = (i - (mla_nu-1)/2 + shift) 2 r_mla,
+ *                t = (j - (mla_nv-1)/2) sqrt(3) r_mla) whose lenslets have
+ *                three focal lengths f_hex_mm[type], type = (q - r) mod 3 in
+ *                hexagonal axial coordinates (r = j - mla_nv/2,
+ *                q = i + shift - r/2), so that neighbours differ.  A pixel
+ *                sums the light through every lenslet (the sum over
+ *                microlenses of the plenoptic-camera section).  The library
+ *                visits, per pixel, the 3 x 3 lenslets around it (nearest
+ *                row +-1, nearest lenslet of each row +-1) and rejects
+ *                cameras for which light could arrive from farther:
+ *                (e hd + e (r_main + k r_mla)) / (1 + e) must stay below
+ *                1.5 sqrt(3) r_mla, with e = d_mla_det/d_mla, hd the
+ *                detector's half diagonal (pixel centres) and k the largest
+ *                |1 + d_mla/d_mla_det - d_mla/f|.  rays_u*rays_v <= 7.
  * Rays are traced from each pixel centre through rays_u x rays_v angular
  * samples -- the centres of a grid over the aperture's bounding square
- * (main lens for single-lens cameras, the pixel's own lenslet for plenoptic
- * ones); samples outside the circular aperture, or a plenoptic ray that
- * misses the main lens, are occluded but still count in the 1/R mean.
+ * (main lens for single-lens cameras, the pixel's own lenslet for square
+ * plenoptic ones, each visited lenslet for hexagonal ones); samples outside
+ * the circular aperture, or a plenoptic ray that misses the main lens, are
+ * occluded but still count in the 1/R mean.
  * Each ray is integrated with `samples` midpoint samples over its segment
  * inside the grid.  Camera point (s,t,z) is world point
  * lens_center + s e_s + t e_t + z e_z, axes = {e_s, e_t, e_z} (orthonormal,
  * right-handed), and the scene is at z > 0. */
 typedef struct ltm_camera {
-    uint32_t kind;              /* LTM_SINGLE_LENS or LTM_PLENOPTIC */
+    uint32_t kind;              /* LTM_SINGLE_LENS, LTM_PLENOPTIC or LTM_PLENOPTIC_HEX */
     uint32_t det_nu, det_nv;    /* detector pixels */
-    uint32_t mla_nu, mla_nv;    /* plenoptic only: lenslets; det_n* multiples */
+    uint32_t mla_nu, mla_nv;    /* plenoptic only: lenslets (square: det_n* multiples) */
     uint32_t rays_u, rays_v;    /* angular samples per pixel, R = rays_u*rays_v <= 64 */
     uint32_t samples;           /* S >= 1 */
     double pixel_pitch_mm;
@@ -86,11 +106,12 @@ typedef struct ltm_camera {
     double d_mla_mm, d_mla_det_mm, f_mla_mm, r_mla_mm;  /* plenoptic only */
     double axes[9];
     double lens_center_mm[3];
+    double f_hex_mm[3];         /* hexagonal plenoptic only: focal length per lenslet type */
 } ltm_camera;
 
 /* How one camera's rays are grouped into workgroups.  A tile is a block of
- * tile_u x tile_v lenslets (for single-lens cameras, blocks of
- * block_u x block_v pixels play the lenslets' role).  Its pixels are split
+ * tile_u x tile_v lenslets (for single-lens and hexagonal plenoptic
+ * cameras, blocks of block_u x block_v pixels play the lenslets' role).  Its pixels are split
  * over `splits` workgroups.  `order` holds flags: bit 0 clear puts one
  * lenslet's pixels on adjacent lanes, set walks adjacent lanes across
  * lenslets; bit 1 stops lanes from starting their angular-sample loop at

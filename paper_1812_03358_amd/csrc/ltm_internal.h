@@ -45,16 +45,29 @@ struct BrickRec {
 // and likewise for t with (cv, dv, g_t).  In voxel-index coordinates the
 // ray is q(z') = qA + z' dq with z' the camera depth relative to the anchor,
 //   qA = CA + sigma Es + tau Et,   dq = slope_s Es + slope_t Et + Ez.
+//
+// Hexagonal plenoptic cameras also loop over the 3 x 3 lenslets around each
+// pixel: rv runs over 9 grv (lenslet-major), the angular grid is ru x grv,
+// cu/cv are the visited lenslet's position in pitches (s) and row spacings
+// (t), Ac/Bc/Lc and Act/Bct/Lct scale them, and the g terms depend on the
+// lenslet's type (hAg, hBg, hLg).  For the other kinds grv = rv, Act = Ac,
+// Bct = Bc and Lct = Lc.
 struct CamDev {
     int kind, nu, nv, mu, mv, ku, kv, ru, rv, S;
+    int grv;              // angular-grid rows (rv / 9 for hexagonal cameras)
     int n[3];
     float Ac, Ad, Ag, Bc, Bd, Bg;
+    float Act, Bct;
+    float hAg[3], hBg[3];
+    float rowf, colf;     // hexagonal: pixel pitch / row spacing, pixel pitch / lenslet pitch
+    int hmu, hmv, hmid;   // hexagonal: lenslets per row, rows, mla_nv / 2 (unshifted row parity)
     float CA[3], Es[3], Et[3], Ez[3];
     float zlo;            // lens plane: z' >= zlo
     float invR;
     float inv_ru, inv_rv;
     int need_aperture;    // plenoptic: FP64 main-lens test per ray
     double Lc, Ld, Lg, r2;  // main-lens crossing s_L = Lc cu + Ld du + Lg g; r_main^2
+    double Lct, hLg[3];
     // tiling
     int tile_u, tile_v, order, splits;
     int rotate;           // lanes start their aperture-sample loop at lane mod R

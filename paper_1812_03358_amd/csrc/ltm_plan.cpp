@@ -28,11 +28,19 @@ struct Chain {
     double sL, u2, sigma;
 };
 
-Chain chain(const ltm_camera& c, double dA, double cu, double du, double g)
+Chain chain(const ltm_camera& c, double dA, double cu, double du, double g, double f_hex = 0.0)
 {
     Chain r;
     const double p = c.pixel_pitch_mm;
-    if (c.kind == LTM_SINGLE_LENS) {
+    if (c.kind == LTM_PLENOPTIC_HEX) {
+        const double cm = cu;                           // lenslet centre, mm
+        const double a = cm + c.r_mla_mm * g;           // sample on that lenslet
+        const double sd = du * p;
+        const double u = (a - sd) / c.d_mla_det_mm;     // detector -> MLA
+        const double u1 = u - (a - cm) / f_hex;         // refraction by its type
+        r.sL = a + u1 * c.d_mla_mm;
+        r.u2 = u1 - r.sL / c.f_main_mm;
+    } else if (c.kind == LTM_SINGLE_LENS) {
         const double a = c.r_main_mm * g;              // aperture sample on the lens
         const double sd = du * p;                       // pixel centre
         const double u = (a - sd) / c.d_det_mm;         // propagation D
@@ -65,7 +73,7 @@ ltm_status validate(const ltm_grid* g, const ltm_camera* cams, uint32_t n_cam)
     for (uint32_t i = 0; i < n_cam; ++i) {
         const ltm_camera& c = cams[i];
         const std::string who = "camera " + std::to_string(i) + ": ";
-        if (c.kind != LTM_SINGLE_LENS && c.kind != LTM_PLENOPTIC)
+        if (c.kind != LTM_SINGLE_LENS && c.kind != LTM_PLENOPTIC && c.kind != LTM_PLENOPTIC_HEX)
             return fail(LTM_ERR_INVALID, who + "unknown kind");
         if (c.det_nu == 0 || c.det_nv == 0) return fail(LTM_ERR_INVALID, who + "empty detector");
         if ((uint64_t)c.det_nu * c.det_nv > (1ull << 30))
@@ -78,6 +86,30 @@ ltm_status validate(const ltm_grid* g, const ltm_camera* cams, uint32_t n_cam)
             return fail(LTM_ERR_INVALID, who + "pitch, focal length and radius must be positive");
         if (c.kind == LTM_SINGLE_LENS) {
             if (!(c.d_det_mm > 0)) return fail(LTM_ERR_INVALID, who + "d_det must be positive");
+        } else if (c.kind == LTM_PLENOPTIC_HEX) {
+            if (c.mla_nu == 0 || c.mla_nv == 0 || c.mla_nu > 65536 || c.mla_nv > 65536)
+                return fail(LTM_ERR_INVALID, who + "need 1..65536 lenslets per row and rows");
+            if (!(c.d_mla_mm > 0) || !(c.d_mla_det_mm > 0) || !(c.r_mla_mm > 0))
+                return fail(LTM_ERR_INVALID, who + "lenslet distances and radius must be positive");
+            if (9 * c.rays_u * c.rays_v > (uint32_t)kMaxRays)
+                return fail(LTM_ERR_INVALID, who + "hexagonal cameras need rays_u*rays_v <= 7");
+            double kmax = 0.0;
+            for (int t = 0; t < 3; ++t) {
+                const double f = c.f_hex_mm[t];
+                if (!(f > 0) || !std::isfinite(f))
+                    return fail(LTM_ERR_INVALID, who + "lenslet focal lengths must be positive");
+                kmax = std::max(kmax, std::fabs(1.0 + c.d_mla_mm / c.d_mla_det_mm - c.d_mla_mm / f));
+            }
+            // a pixel d lit through lenslet c satisfies
+            // |d - c| <= (e |d| + e (r_main + k r_mla)) / (1 + e); the 3 x 3
+            // visited lenslets hold every lenslet closer than 1.5 row spacings
+            const double e = c.d_mla_det_mm / c.d_mla_mm;
+            const double hd = 0.5 * c.pixel_pitch_mm *
+                              std::hypot((double)c.det_nu - 1.0, (double)c.det_nv - 1.0);
+            const double reach = (e * hd + e * (c.r_main_mm + kmax * c.r_mla_mm)) / (1.0 + e);
+            if (!(reach < 1.5 * std::sqrt(3.0) * c.r_mla_mm))
+                return fail(LTM_ERR_INVALID, who + "light could reach pixels from beyond the "
+                                                   "3 x 3 lenslets around them");
         } else {
             if (c.mla_nu == 0 || c.mla_nv == 0 || c.det_nu % c.mla_nu || c.det_nv % c.mla_nv)
                 return fail(LTM_ERR_INVALID, who + "detector must be a multiple of the lenslet count");
@@ -99,12 +131,19 @@ ltm_status validate(const ltm_grid* g, const ltm_camera* cams, uint32_t n_cam)
     return LTM_OK;
 }
 
+// Rays each pixel visits: R, or 9 R for hexagonal cameras (3 x 3 lenslets).
+uint64_t rays_per_pixel(const ltm_camera& c)
+{
+    const uint64_t R = (uint64_t)c.rays_u * c.rays_v;
+    return c.kind == LTM_PLENOPTIC_HEX ? 9 * R : R;
+}
+
 ltm_status check_tiling(const ltm_camera& c, const ltm_tiling& t)
 {
     if (t.tile_u == 0 || t.tile_v == 0 || t.splits == 0)
         return fail(LTM_ERR_INVALID, "tiling sizes must be positive");
-    if (c.kind == LTM_SINGLE_LENS && (t.block_u == 0 || t.block_v == 0))
-        return fail(LTM_ERR_INVALID, "single-lens tiling needs block sizes");
+    if (c.kind != LTM_PLENOPTIC && (t.block_u == 0 || t.block_v == 0))
+        return fail(LTM_ERR_INVALID, "single-lens and hexagonal tilings need block sizes");
     if (t.order > 31) return fail(LTM_ERR_INVALID, "tiling order flags must be 0..31");
     if (t.brick_floats > (uint32_t)kMaxBrickFloats)
         return fail(LTM_ERR_INVALID, "brick larger than 64 KiB of LDS");
@@ -116,7 +155,7 @@ ltm_status check_tiling(const ltm_camera& c, const ltm_tiling& t)
     const uint64_t per = (items + t.splits - 1) / t.splits;
     if (per == 0 || per > 8ull * kThreads)
         return fail(LTM_ERR_INVALID, "a workgroup may own at most 2048 pixels of a tile");
-    const uint64_t R = (uint64_t)c.rays_u * c.rays_v;
+    const uint64_t R = rays_per_pixel(c);
     if (per * R > (uint64_t)kMaxRayList)
         return fail(LTM_ERR_INVALID, "a workgroup may own at most 8192 rays (pixels x R)");
     const uint64_t lds = ((per * R * 4 + 15) & ~15ull) + ((per * 8 + 15) & ~15ull) +
@@ -136,8 +175,8 @@ ltm_tiling default_tiling(const ltm_grid& g, const ltm_camera& c, int dir)
     t.splits = 1;
     t.brick_floats = 8192;
     t.chunk_mm = 64.0 * g.pitch_mm;
-    const uint32_t R = c.rays_u * c.rays_v;
-    if (c.kind == LTM_SINGLE_LENS)
+    const uint64_t R = rays_per_pixel(c);
+    if (c.kind != LTM_PLENOPTIC)
         while (t.block_u > 1 && (uint64_t)t.block_u * t.block_v * R > 4096u) {
             t.block_u /= 2;
             t.block_v /= 2;
@@ -179,8 +218,10 @@ void camera_constants(const ltm_grid& g, const ltm_camera& c, CamDev& d)
     d.kind = (int)c.kind;
     d.nu = (int)c.det_nu;
     d.nv = (int)c.det_nv;
+    const bool hex = c.kind == LTM_PLENOPTIC_HEX;
     d.ru = (int)c.rays_u;
-    d.rv = (int)c.rays_v;
+    d.grv = (int)c.rays_v;
+    d.rv = hex ? 9 * (int)c.rays_v : (int)c.rays_v;
     d.S = (int)c.samples;
     d.n[0] = (int)g.nx;
     d.n[1] = (int)g.ny;
@@ -191,14 +232,34 @@ void camera_constants(const ltm_grid& g, const ltm_camera& c, CamDev& d)
     const double* L = c.lens_center_mm;
     // anchor plane: the camera-depth plane through the grid centre (origin)
     const double dA = -dot3(L, ez);
-    const Chain k_c = chain(c, dA, 1, 0, 0), k_d = chain(c, dA, 0, 1, 0), k_g = chain(c, dA, 0, 0, 1);
-    const bool pl = c.kind == LTM_PLENOPTIC;
-    d.Ac = pl ? (float)k_c.sigma : 0.0f;
-    d.Bc = pl ? (float)k_c.u2 : 0.0f;
+    const double fh = hex ? c.f_hex_mm[0] : 0.0;
+    const Chain k_c = chain(c, dA, 1, 0, 0, fh), k_d = chain(c, dA, 0, 1, 0, fh),
+                k_g = chain(c, dA, 0, 0, 1, fh);
+    const bool pl = c.kind != LTM_SINGLE_LENS;
+    // hexagonal: cu counts lenslet pitches along s, cv row spacings along t
+    const double hp = 2.0 * c.r_mla_mm, hh = std::sqrt(3.0) * c.r_mla_mm;
+    const double cs = hex ? hp : 1.0, ct = hex ? hh : 1.0;
+    d.Ac = pl ? (float)(k_c.sigma * cs) : 0.0f;
+    d.Bc = pl ? (float)(k_c.u2 * cs) : 0.0f;
+    d.Act = pl ? (float)(k_c.sigma * ct) : 0.0f;
+    d.Bct = pl ? (float)(k_c.u2 * ct) : 0.0f;
     d.Ad = (float)k_d.sigma;
     d.Bd = (float)k_d.u2;
     d.Ag = (float)k_g.sigma;
     d.Bg = (float)k_g.u2;
+    for (int t = 0; t < 3; ++t) {
+        const Chain k = hex ? chain(c, dA, 0, 0, 1, c.f_hex_mm[t]) : k_g;
+        d.hAg[t] = (float)k.sigma;
+        d.hBg[t] = (float)k.u2;
+        d.hLg[t] = k.sL;
+    }
+    if (hex) {
+        d.rowf = (float)(c.pixel_pitch_mm / hh);
+        d.colf = (float)(c.pixel_pitch_mm / hp);
+        d.hmid = (int)(c.mla_nv / 2);
+        d.hmu = (int)c.mla_nu;
+        d.hmv = (int)c.mla_nv;
+    }
     const double nn[3] = {(double)g.nx, (double)g.ny, (double)g.nz};
     for (int a = 0; a < 3; ++a) {
         d.CA[a] = (float)((L[a] + dA * ez[a]) / g.pitch_mm + 0.5 * nn[a] - 0.5);
@@ -211,7 +272,8 @@ void camera_constants(const ltm_grid& g, const ltm_camera& c, CamDev& d)
     d.inv_ru = (float)(1.0 / c.rays_u);
     d.inv_rv = (float)(1.0 / c.rays_v);
     d.need_aperture = pl ? 1 : 0;
-    d.Lc = pl ? k_c.sL : 0.0;
+    d.Lc = pl ? k_c.sL * cs : 0.0;
+    d.Lct = pl ? k_c.sL * ct : 0.0;
     d.Ld = k_d.sL;
     d.Lg = k_g.sL;
     d.r2 = c.r_main_mm * c.r_main_mm;
@@ -298,7 +360,7 @@ CamDev bound_dev(const ltm_plan* p, const CamHost& c, int dir)
     if (dir == LTM_ADJOINT && !d.adj_f32) d.brick_cap /= 2;   // FP64 brick in the same LDS budget
     if (p->sub_n > 1) {
         // mean over the subset's samples: the view-subset operator (K/|S|) A_S
-        const int R = d.ru * d.rv;
+        const int R = d.ru * d.grv;
         int ns = 0;
         for (int r = 0; r < R; ++r) ns += (r % (int)p->sub_n == (int)p->sub_i);
         d.sub_n = (int)p->sub_n;

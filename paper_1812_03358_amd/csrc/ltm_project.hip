@@ -59,29 +59,52 @@ __device__ __forceinline__ bool item_pixel(const CamDev& c, int tile, int item, 
 // missing the main lens -- decided in FP64) or misses the voxel box.
 __device__ __forceinline__ bool make_ray(const CamDev& c, int iu, int iv, int ru, int rv, Ray& r)
 {
-    const int a = 2 * ru + 1 - c.ru, b = 2 * rv + 1 - c.rv;
-    if ((long long)a * a * c.rv * c.rv + (long long)b * b * c.ru * c.ru >
-        (long long)c.ru * c.ru * c.rv * c.rv)
+    // hexagonal cameras: rv = lenslet * grv + angular row (3 x 3 lenslets)
+    int nb = 0;
+    if (c.kind == LTM_PLENOPTIC_HEX) {
+        nb = rv / c.grv;
+        rv -= nb * c.grv;
+    }
+    const int a = 2 * ru + 1 - c.ru, b = 2 * rv + 1 - c.grv;
+    if ((long long)a * a * c.grv * c.grv + (long long)b * b * c.ru * c.ru >
+        (long long)c.ru * c.ru * c.grv * c.grv)
         return false;
     if (c.sub_n > 1 && (ru + c.ru * rv) % c.sub_n != c.sub_i) return false;
     const float gs = (float)a / (float)c.ru;
-    const float gt = (float)b / (float)c.rv;
-    float cu = 0.0f, cv = 0.0f;
+    const float gt = (float)b / (float)c.grv;
+    const float du = (float)iu + 0.5f - 0.5f * (float)c.nu;
+    const float dv = (float)iv + 0.5f - 0.5f * (float)c.nv;
+    float cu = 0.0f, cv = 0.0f, Ag = c.Ag, Bg = c.Bg;
+    double Lg = c.Lg;
     if (c.kind == LTM_PLENOPTIC) {
         cu = (float)(iu / c.ku) + 0.5f - 0.5f * (float)c.mu;
         cv = (float)(iv / c.kv) + 0.5f - 0.5f * (float)c.mv;
+    } else if (c.kind == LTM_PLENOPTIC_HEX) {
+        // nearest row +-1, then that row's nearest lenslet +-1
+        const int j = (int)rintf(fmaf(dv, c.rowf, 0.5f * (float)(c.hmv - 1))) + nb / 3 - 1;
+        if (j < 0 || j >= c.hmv) return false;
+        const int rr = j - c.hmid;
+        const int odd = rr & 1;
+        const float shift = 0.5f * (float)odd - 0.5f * (float)(c.hmu - 1);
+        const int i = (int)rintf(fmaf(du, c.colf, -shift)) + nb % 3 - 1;
+        if (i < 0 || i >= c.hmu) return false;
+        cu = (float)i + shift;                          // exact half-integers
+        cv = (float)j - 0.5f * (float)(c.hmv - 1);
+        int type = ((2 * i + odd - rr) / 2 - rr) % 3;
+        type += type < 0 ? 3 : 0;
+        Ag = type == 0 ? c.hAg[0] : (type == 1 ? c.hAg[1] : c.hAg[2]);
+        Bg = type == 0 ? c.hBg[0] : (type == 1 ? c.hBg[1] : c.hBg[2]);
+        Lg = type == 0 ? c.hLg[0] : (type == 1 ? c.hLg[1] : c.hLg[2]);
     }
-    const float du = (float)iu + 0.5f - 0.5f * (float)c.nu;
-    const float dv = (float)iv + 0.5f - 0.5f * (float)c.nv;
     if (c.need_aperture) {
-        const double sL = c.Lc * (double)cu + c.Ld * (double)du + c.Lg * (double)gs;
-        const double tL = c.Lc * (double)cv + c.Ld * (double)dv + c.Lg * (double)gt;
+        const double sL = c.Lc * (double)cu + c.Ld * (double)du + Lg * (double)gs;
+        const double tL = c.Lct * (double)cv + c.Ld * (double)dv + Lg * (double)gt;
         if (sL * sL + tL * tL > c.r2) return false;
     }
-    const float sig = fmaf(c.Ac, cu, fmaf(c.Ad, du, c.Ag * gs));
-    const float tau = fmaf(c.Ac, cv, fmaf(c.Ad, dv, c.Ag * gt));
-    const float us = fmaf(c.Bc, cu, fmaf(c.Bd, du, c.Bg * gs));
-    const float vs = fmaf(c.Bc, cv, fmaf(c.Bd, dv, c.Bg * gt));
+    const float sig = fmaf(c.Ac, cu, fmaf(c.Ad, du, Ag * gs));
+    const float tau = fmaf(c.Act, cv, fmaf(c.Ad, dv, Ag * gt));
+    const float us = fmaf(c.Bc, cu, fmaf(c.Bd, du, Bg * gs));
+    const float vs = fmaf(c.Bct, cv, fmaf(c.Bd, dv, Bg * gt));
     float zl = c.zlo, zh = FLT_MAX;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {

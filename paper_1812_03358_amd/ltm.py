@@ -36,6 +36,9 @@ class Grid(ctypes.Structure):
                 ("reserved", ctypes.c_uint32), ("pitch_mm", ctypes.c_double)]
 
 
+ABI_VERSION = 2
+
+
 class Camera(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_uint32), ("det_nu", ctypes.c_uint32), ("det_nv", ctypes.c_uint32),
                 ("mla_nu", ctypes.c_uint32), ("mla_nv", ctypes.c_uint32),
@@ -46,7 +49,8 @@ class Camera(ctypes.Structure):
                 ("d_det_mm", ctypes.c_double),
                 ("d_mla_mm", ctypes.c_double), ("d_mla_det_mm", ctypes.c_double),
                 ("f_mla_mm", ctypes.c_double), ("r_mla_mm", ctypes.c_double),
-                ("axes", ctypes.c_double * 9), ("lens_center_mm", ctypes.c_double * 3)]
+                ("axes", ctypes.c_double * 9), ("lens_center_mm", ctypes.c_double * 3),
+                ("f_hex_mm", ctypes.c_double * 3)]
 
 
 class Tiling(ctypes.Structure):
@@ -150,6 +154,9 @@ def lib():
                 continue
             f.restype = res
             f.argtypes = args
+        if h.ltm_abi_version() != ABI_VERSION:
+            raise RuntimeError(f"{LIB_PATH} has ABI version {h.ltm_abi_version()}, the binding "
+                               f"expects {ABI_VERSION}: rebuild it")
         _lib = h
     return _lib
 
@@ -195,7 +202,8 @@ def make_cameras(cams) -> ctypes.Array:
                         c["rays_u"], c["rays_v"], c["samples"], c["pixel_pitch"],
                         c["f_main"], c["r_main"], c["d_det"], c["d_mla"], c["d_mla_det"],
                         c["f_mla"], c["r_mla"], (ctypes.c_double * 9)(*c["axes"]),
-                        (ctypes.c_double * 3)(*c["lens_center"]))
+                        (ctypes.c_double * 3)(*c["lens_center"]),
+                        (ctypes.c_double * 3)(*c.get("f_hex", (0.0, 0.0, 0.0))))
     return arr
 
 

@@ -35,7 +35,7 @@ def test_every_declared_function_is_exported(L):
 
 
 def test_abi_version(L):
-    assert L.lib().ltm_abi_version() == 1
+    assert L.lib().ltm_abi_version() == L.ABI_VERSION == 2
 
 
 def _create(L, g, cams):
@@ -112,3 +112,32 @@ def test_binding_fails_loudly_without_library(L, monkeypatch, tmp_path):
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         L.lib()
+
+
+def test_hexagonal_camera_validation(L):
+    import math
+    g = W.grid(100, 1.0)
+    ok = W.hex_plenoptic_camera()                        # the paper's 2048^2 camera
+    assert _create(L, g, [ok])[0] == 0
+    st, msg = _create(L, g, [W.hex_plenoptic_camera(rays=(3, 3))])
+    assert st == L.LTM_ERR_INVALID and "<= 7" in msg
+    bad = W.hex_plenoptic_camera()
+    bad["f_hex"] = [2.8, -3.0, 3.2]
+    st, msg = _create(L, g, [bad])
+    assert st == L.LTM_ERR_INVALID and "focal" in msg
+    # the reach rule: accepted exactly while the bound stays below 1.5 row spacings
+    limit = 1.5 * math.sqrt(3) * W.PL_RMU
+
+    def reach(c):
+        e = c["d_mla_det"] / c["d_mla"]
+        k = max(abs(1 + c["d_mla"] / c["d_mla_det"] - c["d_mla"] / f) for f in c["f_hex"])
+        hd = 0.5 * c["pixel_pitch"] * math.hypot(c["det_nu"] - 1, c["det_nv"] - 1)
+        return (e * hd + e * (c["r_main"] + k * c["r_mla"])) / (1 + e)
+
+    for det in (1024, 2048, 2064, 2200, 3000):
+        c = W.hex_plenoptic_camera(det)
+        st, msg = _create(L, g, [c])
+        assert (st == 0) == (reach(c) < limit), (det, msg)
+        if st:
+            assert "3 x 3" in msg
+    assert reach(W.hex_plenoptic_camera(2048)) < limit < reach(W.hex_plenoptic_camera(3000))
