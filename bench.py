@@ -377,7 +377,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="plenoptic_128",
                     choices=["plenoptic_128", "thin_lens_32", "differentiable_256", "batched_48",
-                             "recon_plenoptic_128", "recon_three_camera_100", "warm_start_128"])
+                             "recon_plenoptic_128", "recon_three_camera_100", "warm_start_128",
+                             "hex_plenoptic_100"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", action="store_true")
@@ -407,6 +408,12 @@ def main():
         out = run_single(args, W.config_differentiable(), "differentiable_256: 256^3 flame, 4 "
                          "plenoptic cameras 2048^2 (128^2 lenslets) at 0/30/60/90 deg, 2x1 rays, "
                          "512 samples; one A x + one A^T y per step")
+    elif args.workload == "hex_plenoptic_100":
+        out = run_single(args, W.config_hex_plenoptic(), "hex_plenoptic_100: 100^3 flame (1 mm "
+                         "voxels), plenoptic camera 2048^2 px of 5 um behind a hexagonal 53x61 "
+                         "array of 2.8/3.0/3.2 mm lenslets, light summed over all lenslets (3x3 "
+                         "visited per pixel), 2x2 rays/lenslet, 200 samples/ray; one A x + one "
+                         "A^T y per step")
     elif args.workload == "batched_48":
         out = run_batched(args)
     elif args.workload == "warm_start_128":

@@ -34,7 +34,7 @@ def candidates(plan, cam_index: int, direction: int):
     """Candidate tilings (dicts of ltm_tiling fields) for one camera."""
     c = plan.cameras[cam_index]
     pitch = plan.grid["pitch"]
-    R = c["rays_u"] * c["rays_v"]
+    R = c["rays_u"] * c["rays_v"] * (9 if c["kind"] == 2 else 1)   # hexagonal: 3x3 lenslets
     out = []
     plen = c["kind"] == 1
     k = (c["det_nu"] // c["mla_nu"]) * (c["det_nv"] // c["mla_nv"]) if plen else 1

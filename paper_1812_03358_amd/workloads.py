@@ -271,6 +271,15 @@ def config_warm_start():
                          for phi in (0.0, 90.0)])
 
 
+def config_hex_plenoptic():
+    """The simulated plenoptic table as listed: 2048^2 px of 5 um behind a
+    hexagonal 53 x 61 array of three focal lengths, light summed over all
+    lenslets; 100^3 flame at 1 mm, 2x2 angular samples, 200 samples per ray."""
+    return dict(name="hex_plenoptic_100", grid=grid(100, 1.0),
+                cameras=[hex_plenoptic_camera(2048, None, (2, 2), 200)],
+                volume=lambda: flame(100, 5), noise_seed=13)
+
+
 def config_three_camera(n: int = 100, det_pl: int = 2048, mla: int = 128, det_tl: int = 1024,
                         rays=(8, 8), samples: int = 200):
     """One plenoptic camera head-on and two single-lens cameras at +-30 deg
