@@ -1,0 +1,219 @@
+"""FP64 reference of the paper's own discretization: the L2-projected light
+field transport with Dirac or pillbox angular bases, for a single-lens camera
+looking head-on at a voxel volume collapsed into slices.
+
+TEST INFRASTRUCTURE ONLY (same rules as the rest of ``oracle/``): imported by
+tests/ and the benchmark's CPU leg, never by the product package.
+
+What it computes, in the paper's notation:
+  * optics    -- 3x3 affine ray maps on (s, u, 1) built from the propagation
+                 T_d and the refraction R_f of the table of common affine
+                 optical transformations; the angular plane is the main lens;
+                 X^{0q} = (T_{z_q} o R_f)^{-1} for a slice at depth z_q,
+                 X^{0d} = T_D for the detector, X^{pq} = (X^{0p})^{-1} o X^{0q}
+                 (camera-model and light-transport sections);
+  * transport -- the entries of B^{pq}_k from the Dirac and the pillbox
+                 transport tables (blur kernel g, its breakpoints tau,
+                 height h and magnification 1/alpha), integrated over the
+                 source pixel; the s and t factors multiply (Kronecker
+                 separability of the transport);
+  * slices    -- each voxel slice of thickness dz radiates the light field
+                 w_k = dz x_slice for every angular basis k (object-model
+                 section, small-angle collapse);
+  * occlusion -- angular cells whose centre lies outside the lens disc are
+                 masked (occlusion section, the aperture rasterized on the
+                 angular grid);
+  * detector  -- f^d_k = B^{ds}_k w_k / V^d, and a pixel reads the mean over
+                 the K angular cells of f^d_k.  The measurement section
+                 writes sqrt(V^d) sum_k f^d_k; the constant is replaced by 1/K
+                 so that the values share the units of the ray-driven
+                 operator (mean over rays of line integrals), a global scale
+                 the camera gains absorb.
+The angular grid is Ks x Kt cells of size 2 r_main / K over the lens's
+bounding square, as the ray-driven operator places its rays.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+DIRAC = 0
+PILLBOX = 1
+
+
+# --------------------------------------------------------------------------
+# affine optics on (s, u, 1)
+# --------------------------------------------------------------------------
+def T(d: float) -> np.ndarray:
+    """Propagation by d: s' = s + d u."""
+    return np.array([[1.0, d, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+
+
+def R(f: float, c: float = 0.0) -> np.ndarray:
+    """Thin-lens refraction (focal length f, centre c): u' = u - (s - c)/f."""
+    return np.array([[1.0, 0.0, 0.0], [-1.0 / f, 1.0, c / f], [0.0, 0.0, 1.0]])
+
+
+def single_lens_maps(z_q: float, D: float, F: float):
+    """(X^{0q}, X^{pq}, X^{0p}) for a slice at camera depth z_q, the detector
+    D behind a lens of focal length F (rays run from the detector into the
+    scene, z increasing)."""
+    X0q = np.linalg.inv(T(z_q) @ R(F))
+    X0p = T(D)
+    Xpq = np.linalg.inv(X0p) @ X0q
+    return X0q, Xpq, X0p
+
+
+# --------------------------------------------------------------------------
+# one-dimensional transport factors (the tables)
+# --------------------------------------------------------------------------
+def _overlap(a0, a1, b0, b1):
+    return np.maximum(0.0, np.minimum(a1, b1) - np.maximum(a0, b0))
+
+
+def _trapezoid_integral(lo, hi, t):
+    """Integral over [lo, hi] of the trapezoid rising on [t1, t2], flat (1)
+    on [t2, t3] and falling on [t3, t4]; vectorized over lo/hi."""
+    t1, t2, t3, t4 = t
+
+    def ramp_up(x):           # integral from t1 to x of (s - t1)/(t2 - t1), x in [t1, t2]
+        return 0.5 * (x - t1) ** 2 / (t2 - t1) if t2 > t1 else 0.0 * x
+
+    def ramp_dn(x):           # integral from t3 to x of 1 - (s - t3)/(t4 - t3)
+        return ((x - t3) - 0.5 * (x - t3) ** 2 / (t4 - t3)) if t4 > t3 else 0.0 * x
+
+    def G(x):                 # antiderivative from -inf
+        x = np.asarray(x, dtype=np.float64)
+        out = np.zeros_like(x)
+        m = (x > t1) & (x <= t2)
+        out[m] = ramp_up(x[m])
+        up = 0.5 * (t2 - t1)
+        m = (x > t2) & (x <= t3)
+        out[m] = up + (x[m] - t2)
+        m = (x > t3) & (x <= t4)
+        out[m] = up + (t3 - t2) + ramp_dn(x[m])
+        m = x > t4
+        out[m] = up + (t3 - t2) + 0.5 * (t4 - t3)
+        return out
+
+    return G(hi) - G(lo)
+
+
+def transport_factor(basis: int, Xpq, X0q, sk: float, d0: float, si, dp: float, sj, dq: float,
+                     axis: int = 0) -> np.ndarray:
+    """[B^{pq}_{k,axis}]_{ij}: destination pixels centred at si (size dp) on
+    plane p, source pixels centred at sj (size dq) on plane q, angular cell
+    centred at sk (size d0) on the angular plane.  ``Xpq``/``X0q`` are the
+    3x3 affine maps of that axis."""
+    si = np.asarray(si, dtype=np.float64)
+    sj = np.asarray(sj, dtype=np.float64)
+    pss, psu, pbar = Xpq[0, 0], Xpq[0, 1], Xpq[0, 2]
+    qss, qsu, qbar = X0q[0, 0], X0q[0, 1], X0q[0, 2]
+    if basis == DIRAC:
+        alpha = pss - qss * psu / qsu
+        beta = pbar + psu * (sk - qbar) / qsu
+        tau = np.sort([(0.5 * dp - beta) / alpha, (-0.5 * dp - beta) / alpha])
+        h = d0 / abs(qsu)
+        mag = 1.0 / alpha
+        lo = si[:, None] * mag + tau[0]
+        hi = si[:, None] * mag + tau[1]
+        return h * _overlap(sj[None, :] - 0.5 * dq, sj[None, :] + 0.5 * dq, lo, hi)
+    alpha = pss - psu * qss / qsu
+    beta = psu / qsu
+    gamma = pbar - psu * qbar / qsu
+    tau = np.sort([(sp * 0.5 * dp - beta * (sk - s0 * 0.5 * d0) - gamma) / alpha
+                   for sp in (1.0, -1.0) for s0 in (1.0, -1.0)])
+    h = abs(d0 / qsu) if psu == 0.0 else min(abs(d0 / qsu), abs(dp / psu))
+    mag = 1.0 / alpha
+    lo = sj[None, :] - 0.5 * dq - si[:, None] * mag
+    return h * _trapezoid_integral(lo, lo + dq, tau)
+
+
+def detector_volume(basis: int, X0p, dp: float, d0: float) -> float:
+    """One axis of V^p (the Dirac table's product form, or the pillbox
+    table's 2 m h)."""
+    ss, su = X0p[0, 0], X0p[0, 1]
+    if basis == DIRAC:
+        return dp * abs(d0 / su)
+    m = max(d0 / (2.0 * abs(su)), dp * abs(ss / su) / 2.0)
+    h = min(dp, d0 / abs(ss))
+    return 2.0 * m * h
+
+
+# --------------------------------------------------------------------------
+# the camera operator
+# --------------------------------------------------------------------------
+def _check_head_on(cam: dict):
+    if cam["kind"] != 0:
+        raise ValueError("the transport operator models single-lens cameras")
+    ax = np.asarray(cam["axes"], dtype=np.float64)
+    if not np.array_equal(ax, np.eye(3).reshape(-1)) or cam["lens_center"][0] != 0.0 or \
+            cam["lens_center"][1] != 0.0:
+        raise ValueError("the transport operator needs a head-on camera on the z axis")
+
+
+def angular_cells(cam: dict):
+    """Centres (s_k, t_k) of the unmasked angular cells and the cell sizes."""
+    Ks, Kt, r = cam["rays_u"], cam["rays_v"], cam["r_main"]
+    d0s, d0t = 2.0 * r / Ks, 2.0 * r / Kt
+    cells = []
+    for kt in range(Kt):
+        for ks in range(Ks):
+            s = (ks + 0.5) * d0s - r
+            t = (kt + 0.5) * d0t - r
+            if s * s + t * t <= r * r:
+                cells.append((s, t))
+    return cells, d0s, d0t
+
+
+def slice_factors(g: dict, cam: dict, basis: int):
+    """Per slice iz and unmasked cell k: (Bs [nu, nx], Bt [nv, ny]) and the
+    scale dz / (K V^d)."""
+    _check_head_on(cam)
+    nx, ny, nz, dx = g["nx"], g["ny"], g["nz"], g["pitch"]
+    nu, nv, dp = cam["det_nu"], cam["det_nv"], cam["pixel_pitch"]
+    L = -cam["lens_center"][2]
+    D, F = cam["d_det"], cam["f_main"]
+    cells, d0s, d0t = angular_cells(cam)
+    K = cam["rays_u"] * cam["rays_v"]
+    si = (np.arange(nu) + 0.5 - 0.5 * nu) * dp
+    ti = (np.arange(nv) + 0.5 - 0.5 * nv) * dp
+    sj = (np.arange(nx) + 0.5 - 0.5 * nx) * dx
+    tj = (np.arange(ny) + 0.5 - 0.5 * ny) * dx
+    X0p = T(D)
+    Vd = detector_volume(basis, X0p, dp, d0s) * detector_volume(basis, X0p, dp, d0t)
+    scale = dx / (K * Vd)
+    out = []
+    for iz in range(nz):
+        zq = L + (iz + 0.5 - 0.5 * nz) * dx
+        X0q, Xpq, _ = single_lens_maps(zq, D, F)
+        per = []
+        for sk, tk in cells:
+            Bs = transport_factor(basis, Xpq, X0q, sk, d0s, si, dp, sj, dx)
+            Bt = transport_factor(basis, Xpq, X0q, tk, d0t, ti, dp, tj, dx)
+            per.append((Bs, Bt))
+        out.append(per)
+    return out, scale
+
+
+def project(g: dict, cam: dict, x, basis: int = PILLBOX) -> np.ndarray:
+    """y = A x, image (nv, nu) flattened; x is (nz, ny, nx)."""
+    x = np.asarray(x, dtype=np.float64).reshape(g["nz"], g["ny"], g["nx"])
+    fac, scale = slice_factors(g, cam, basis)
+    y = np.zeros((cam["det_nv"], cam["det_nu"]))
+    for iz, per in enumerate(fac):
+        for Bs, Bt in per:
+            y += Bt @ x[iz] @ Bs.T
+    return (scale * y).reshape(-1)
+
+
+def backproject(g: dict, cam: dict, y, basis: int = PILLBOX) -> np.ndarray:
+    """x = A^T y, volume (nz, ny, nx) flattened."""
+    y = np.asarray(y, dtype=np.float64).reshape(cam["det_nv"], cam["det_nu"])
+    fac, scale = slice_factors(g, cam, basis)
+    x = np.zeros((g["nz"], g["ny"], g["nx"]))
+    for iz, per in enumerate(fac):
+        for Bs, Bt in per:
+            x[iz] += Bt.T @ y @ Bs
+    return (scale * x).reshape(-1)
