@@ -63,8 +63,9 @@ def candidates(plan, cam_index: int, direction: int):
                     splits = max(1, items // per)
                     if items % splits or items // splits > 2048 or items // splits * R > 8192:
                         continue
-                    for order in (1, 3):
-                        for chunk in (8, 16, 32):
+                    # bit 3 staggers sample walks, bit 4 merges a cell's samples
+                    for order in (3, 24, 26, 27):
+                        for chunk in (16, 32):
                             for brick in (8192, 12288):
                                 out.append(dict(tile_u=t, tile_v=t, block_u=blk, block_v=blk,
                                                 order=order, splits=splits, brick_floats=brick,

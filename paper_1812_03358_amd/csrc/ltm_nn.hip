@@ -317,8 +317,9 @@ __global__ void k_mse(const float* __restrict__ x, const float* __restrict__ t, 
     double s = 0.0;
     const float inv = 1.0f / (float)n;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const double dd = (double)x[i] - (double)t[i];   // exact for FP32 inputs
+        s += dd * dd;
         const float d = x[i] - t[i];
-        s += (double)d * d;
         g[i] = x[i] > 0.0f ? 2.0f * d * inv : 0.0f;
     }
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);

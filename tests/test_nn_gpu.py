@@ -153,7 +153,7 @@ def test_pool_relu_mse_adam(nn):
     gg = torch.empty(1000, device="cuda")
     assert lib.ltm_nn_mse(nn._p(torch.from_numpy(p).cuda()), nn._p(torch.from_numpy(t).cuda()), nn._p(gg),
                           nn._p(loss), 1000, None) == 0
-    assert abs(float(loss) - np.mean((p.astype(np.float64) - t) ** 2)) < 1e-9
+    assert abs(float(loss) - np.mean((p.astype(np.float64) - t) ** 2)) < 1e-12
     assert rel(gg.cpu().numpy(), 2 * (p - t) / 1000 * (p > 0)) < 1e-6
     # adam vs torch.optim.Adam (float64, CPU), three steps
     w0 = rng.standard_normal(300)
@@ -173,8 +173,38 @@ def test_pool_relu_mse_adam(nn):
     assert rel(w.cpu().numpy(), wt.detach().numpy()) < 1e-6
 
 
+def _bf16(t):
+    return t.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+
+class _RoundAct(torch.autograd.Function):
+    """BF16 rounding of a stored activation (forward only)."""
+
+    @staticmethod
+    def forward(ctx, t):
+        return _bf16(t)
+
+    @staticmethod
+    def backward(ctx, g):
+        return g
+
+
+class _RoundGrad(torch.autograd.Function):
+    """BF16 rounding of the pre-activation gradient (backward only)."""
+
+    @staticmethod
+    def forward(ctx, t):
+        return t.clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        return _bf16(g)
+
+
 def _torch_net(params, x, n):
-    """The same network in torch float64 on the CPU (autograd reference)."""
+    """The same network in torch float64 on the CPU (autograd reference),
+    rounding where the kernels store BF16: every stored activation, and the
+    gradient with respect to each conv's output; accumulation stays FP64."""
     acts = {"in": x}
     spec = {a[0]: a for a in onn.ARCH}
 
@@ -194,7 +224,8 @@ def _torch_net(params, x, n):
         if c1:
             h = torch.cat([h, acts[ins[1]]], dim=1)
         w, b = params[name]
-        acts[name] = F.relu(F.conv3d(h, tw(w, c0 + c1, ks), b, padding=ks // 2))
+        z = _RoundGrad.apply(F.conv3d(h, tw(w, c0 + c1, ks), b, padding=ks // 2))
+        acts[name] = F.relu(z) if name == "out" else _RoundAct.apply(F.relu(z))
     return acts["out"][0, 0]
 
 
