@@ -362,6 +362,46 @@ ltm_status ltm_nn_prep_input(const float* x, uint16_t* y, uint32_t* scratch, uin
 /* a += b (FP32). */
 ltm_status ltm_nn_add(float* a, const float* b, uint64_t n, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* The paper's own discretization (light-field discretization, light
+ * transport, object-model and camera-model sections; Dirac and pillbox
+ * transport tables), for a single-lens camera looking head-on along +z at the
+ * grid (axes = identity, lens_center = (0, 0, -distance), every slice in front
+ * of the lens).  The volume is collapsed into its nz slices; slice iz at
+ * camera depth z = distance + (iz + 1/2 - nz/2) pitch radiates the light
+ * field dz * x[iz] for every angular cell.  The angular plane is the main
+ * lens, divided into rays_u x rays_v square cells of size 2 r_main / rays_*
+ * over its bounding square; cells whose centre lies outside the lens disc
+ * are masked.  Each cell's transport is the Kronecker product of an s and a
+ * t factor whose entries are the table's blur kernel integrated over the
+ * source voxel; pixel i reads
+ *   y_i = (dz / (K V^d)) sum_slices sum_cells [B_s (x) B_t] x_slice,
+ * K = rays_u * rays_v, V^d the detector basis volume of the table (the
+ * paper's sqrt(V^d) sum over cells replaced by the mean over cells, a global
+ * scale).  A^T uses the same FP32 entries.  Accumulation is FP64 per output.
+ * The library evaluates the entries in FP64 once, at bind time, into banded
+ * FP32 tables in the workspace. */
+enum { LTM_BASIS_DIRAC = 0u, LTM_BASIS_PILLBOX = 1u };
+
+typedef struct ltm_xport ltm_xport;
+
+ltm_status ltm_xport_create(const ltm_grid* grid, const ltm_camera* camera, uint32_t basis,
+                            ltm_xport** out);
+void ltm_xport_destroy(ltm_xport* t);
+/* Workspace for the banded tables and the nz * rays_v * det_nv * nx FP32
+ * intermediate of the two filtering passes. */
+ltm_status ltm_xport_workspace_bytes(const ltm_xport* t, uint64_t* bytes);
+/* Binds caller-owned device memory (>= workspace_bytes, 256-byte aligned)
+ * and uploads the tables; synchronizes the stream. */
+ltm_status ltm_xport_bind_workspace(ltm_xport* t, void* workspace, uint64_t bytes, void* stream);
+/* y (det_nv x det_nu) = A x; x[nz][ny][nx]. */
+ltm_status ltm_xport_project(ltm_xport* t, const float* x, float* y, void* stream);
+/* x = A^T y (overwrites x). */
+ltm_status ltm_xport_backproject(ltm_xport* t, const float* y, float* x, void* stream);
+/* Band widths of the four tables: t-factor rows, s-factor rows (cells of
+ * one row summed), and their transposes. */
+ltm_status ltm_xport_bands(const ltm_xport* t, uint32_t bands[4]);
+
 #ifdef __cplusplus
 }
 #endif

@@ -127,6 +127,9 @@ ltm_status fail(ltm_status s, const std::string& msg);
 ltm_status hip_fail(hipError_t e, const char* what);
 void clear_error();
 
+// descriptor checks shared by every operator built from grid and cameras
+ltm_status validate_cameras(const ltm_grid* g, const ltm_camera* cams, uint32_t n_cam);
+
 // kernel launchers (ltm_project.hip)
 hipError_t launch_setup(const CamDev& c, int dir, hipStream_t s);
 hipError_t launch_project(const CamDev& c, const float* x, float* y, hipStream_t s);

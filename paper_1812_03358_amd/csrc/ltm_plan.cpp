@@ -340,6 +340,11 @@ void layout(ltm_plan* p)
 
 }  // namespace
 
+ltm_status validate_cameras(const ltm_grid* g, const ltm_camera* cams, uint32_t n_cam)
+{
+    return validate(g, cams, n_cam);
+}
+
 ltm_status fail(ltm_status s, const std::string& msg)
 {
     g_err = msg;

@@ -1,0 +1,153 @@
+// Light-field transport operator (the paper's Dirac / pillbox transport for a
+// head-on single-lens camera) as separable filtering passes on gfx950.
+//
+// Forward, per (slice iz, angular row kt):
+//   minor pass  M[iz][kt][v][ix] = sum_iy Bt(iz,kt)[v][iy] x[iz][iy][ix]
+//   major pass  y[v][u]          = sum_{iz,kt} sum_ix Cs(iz,kt)[u][ix] M[iz][kt][v][ix]
+// where Cs(iz,kt) is the sum of the s factors of the row's unmasked cells
+// (the cells of one angular row share their t factor).  The adjoint runs the
+// transposed tables in the opposite order.  Every output has one writer
+// (no atomics): the minor passes write one intermediate value per thread and
+// the major passes accumulate a whole output in FP64 registers.
+#include "ltm_xport.h"
+
+namespace ltm {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kRowsPerThread = 4;   // forward major pass: detector rows per thread
+
+// M[p][v][ix] = sum_k bt.w[p][k][v] * x[iz][start + k][ix],  p = iz * kt + kt_i
+__global__ __launch_bounds__(kBlock) void k_minor_fwd(XportDev d, const float* __restrict__ x)
+{
+    const size_t total = (size_t)d.nz * d.kt * d.nv * d.nx;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * kBlock) {
+        const int ix = (int)(i % d.nx);
+        const size_t r = i / d.nx;
+        const int v = (int)(r % d.nv);
+        const size_t p = r / d.nv;
+        const size_t iz = p / d.kt;
+        const int st = d.bt.start[p * d.nv + v];
+        const float* w = d.bt.w + p * d.bt.width * (size_t)d.nv + v;
+        const float* xs = x + iz * d.ny * (size_t)d.nx + ix;
+        float acc = 0.0f;
+        for (int k = 0; k < d.bt.width; ++k) {
+            const int iy = st + k;
+            if (iy < d.ny) acc = fmaf(w[(size_t)k * d.nv], xs[(size_t)iy * d.nx], acc);
+        }
+        d.mid[i] = acc;
+    }
+}
+
+// y[v][u] for kRowsPerThread consecutive rows v of one column u.
+__global__ __launch_bounds__(kBlock) void k_major_fwd(XportDev d, float* __restrict__ y)
+{
+    const int vblocks = (d.nv + kRowsPerThread - 1) / kRowsPerThread;
+    const size_t total = (size_t)vblocks * d.nu;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * kBlock) {
+        const int u = (int)(i % d.nu);
+        const int v0 = (int)(i / d.nu) * kRowsPerThread;
+        double acc[kRowsPerThread];
+#pragma unroll
+        for (int r = 0; r < kRowsPerThread; ++r) acc[r] = 0.0;
+        const size_t pairs = (size_t)d.nz * d.kt;
+        for (size_t p = 0; p < pairs; ++p) {
+            const int st = d.cs.start[p * d.nu + u];
+            const float* w = d.cs.w + p * d.cs.width * (size_t)d.nu + u;
+            const float* m = d.mid + p * d.nv * (size_t)d.nx;
+            for (int k = 0; k < d.cs.width; ++k) {
+                const int ix = st + k;
+                if (ix >= d.nx) break;
+                const float c = w[(size_t)k * d.nu];
+#pragma unroll
+                for (int r = 0; r < kRowsPerThread; ++r)
+                    if (v0 + r < d.nv) acc[r] += (double)(c * m[(size_t)(v0 + r) * d.nx + ix]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kRowsPerThread; ++r)
+            if (v0 + r < d.nv) y[(size_t)(v0 + r) * d.nu + u] = (float)acc[r];
+    }
+}
+
+// M[p][v][ix] = sum_k cst.w[p][k][ix] * y[v][start + k]
+__global__ __launch_bounds__(kBlock) void k_major_adj(XportDev d, const float* __restrict__ y)
+{
+    const size_t total = (size_t)d.nz * d.kt * d.nv * d.nx;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * kBlock) {
+        const int ix = (int)(i % d.nx);
+        const size_t r = i / d.nx;
+        const int v = (int)(r % d.nv);
+        const size_t p = r / d.nv;
+        const int st = d.cst.start[p * d.nx + ix];
+        const float* w = d.cst.w + p * d.cst.width * (size_t)d.nx + ix;
+        const float* yr = y + (size_t)v * d.nu;
+        double acc = 0.0;
+        for (int k = 0; k < d.cst.width; ++k) {
+            const int u = st + k;
+            if (u < d.nu) acc += (double)(w[(size_t)k * d.nx] * yr[u]);
+        }
+        d.mid[i] = (float)acc;
+    }
+}
+
+// x[iz][iy][ix] = sum_kt sum_k btt.w[p][k][iy] * M[p][start + k][ix]
+__global__ __launch_bounds__(kBlock) void k_minor_adj(XportDev d, float* __restrict__ x)
+{
+    const size_t total = (size_t)d.nz * d.ny * d.nx;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * kBlock) {
+        const int ix = (int)(i % d.nx);
+        const size_t r = i / d.nx;
+        const int iy = (int)(r % d.ny);
+        const size_t iz = r / d.ny;
+        double acc = 0.0;
+        for (int kt = 0; kt < d.kt; ++kt) {
+            const size_t p = iz * d.kt + kt;
+            const int st = d.btt.start[p * d.ny + iy];
+            const float* w = d.btt.w + p * d.btt.width * (size_t)d.ny + iy;
+            const float* m = d.mid + p * d.nv * (size_t)d.nx + ix;
+            for (int k = 0; k < d.btt.width; ++k) {
+                const int v = st + k;
+                if (v < d.nv) acc += (double)(w[(size_t)k * d.ny] * m[(size_t)v * d.nx]);
+            }
+        }
+        x[i] = (float)acc;
+    }
+}
+
+unsigned grid_for(size_t n)
+{
+    const size_t b = (n + kBlock - 1) / kBlock;
+    return (unsigned)(b < 65536 ? (b ? b : 1) : 65536);
+}
+
+}  // namespace
+
+hipError_t launch_xport_project(const XportDev& d, const float* x, float* y, hipStream_t s)
+{
+    const size_t nm = (size_t)d.nz * d.kt * d.nv * d.nx;
+    hipLaunchKernelGGL(k_minor_fwd, dim3(grid_for(nm)), dim3(kBlock), 0, s, d, x);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t ny = (size_t)((d.nv + kRowsPerThread - 1) / kRowsPerThread) * d.nu;
+    hipLaunchKernelGGL(k_major_fwd, dim3(grid_for(ny)), dim3(kBlock), 0, s, d, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_xport_backproject(const XportDev& d, const float* y, float* x, hipStream_t s)
+{
+    const size_t nm = (size_t)d.nz * d.kt * d.nv * d.nx;
+    hipLaunchKernelGGL(k_major_adj, dim3(grid_for(nm)), dim3(kBlock), 0, s, d, y);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t nx = (size_t)d.nz * d.ny * d.nx;
+    hipLaunchKernelGGL(k_minor_adj, dim3(grid_for(nx)), dim3(kBlock), 0, s, d, x);
+    return hipGetLastError();
+}
+
+}  // namespace ltm

@@ -139,6 +139,19 @@ _NN_SIGS = {
 }
 _SIGS.update(_NN_SIGS)
 
+_XPORT_SIGS = {
+    "ltm_xport_create": (ctypes.c_int, [ctypes.POINTER(Grid), ctypes.POINTER(Camera), _U32,
+                                        ctypes.POINTER(_VP)]),
+    "ltm_xport_destroy": (None, [_VP]),
+    "ltm_xport_workspace_bytes": (ctypes.c_int, [_VP, ctypes.POINTER(_U64)]),
+    "ltm_xport_bind_workspace": (ctypes.c_int, [_VP, _VP, _U64, _VP]),
+    "ltm_xport_project": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "ltm_xport_backproject": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "ltm_xport_bands": (ctypes.c_int, [_VP, ctypes.POINTER(_U32)]),
+}
+_SIGS.update(_XPORT_SIGS)
+BASIS_DIRAC, BASIS_PILLBOX = 0, 1
+
 
 def lib():
     """The loaded library; raises if libltm.so has not been built."""
@@ -413,3 +426,50 @@ def reg_grad_add(grid: dict, z: torch.Tensor, g: torch.Tensor, beta: float, psi_
     _check(lib().ltm_reg_grad_add(ctypes.byref(gg), psi_kind, beta, delta, _ptr(z, numel=n),
                                   _ptr(g, numel=n), _stream(stream)))
     return g
+
+
+class Transport:
+    """The paper's L2-projected light-field transport (Dirac or pillbox
+    angular basis) for one head-on single-lens camera; see ltm_xport_* in
+    include/ltm.h.  Tables and the filtering intermediate live in a device
+    workspace owned by this object."""
+
+    def __init__(self, grid: dict, camera: dict, basis: int = BASIS_PILLBOX, device="cuda"):
+        self.grid = dict(grid)
+        self.camera = dict(camera)
+        gg, cc = make_grid(grid), make_cameras([camera])
+        h = ctypes.c_void_p()
+        _check(lib().ltm_xport_create(ctypes.byref(gg), cc, int(basis), ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_uint64()
+        _check(lib().ltm_xport_workspace_bytes(h, ctypes.byref(n)))
+        self.workspace = torch.empty(max(int(n.value), 256), dtype=torch.uint8, device=device)
+        _check(lib().ltm_xport_bind_workspace(h, ctypes.c_void_p(self.workspace.data_ptr()),
+                                              self.workspace.numel(), _stream(None)))
+        self.n_voxels = grid["nx"] * grid["ny"] * grid["nz"]
+        self.n_meas = camera["det_nu"] * camera["det_nv"]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.ltm_xport_destroy(h)
+            self._h = None
+
+    def bands(self):
+        b = (ctypes.c_uint32 * 4)()
+        _check(lib().ltm_xport_bands(self._h, b))
+        return list(b)
+
+    def project(self, x: torch.Tensor, y: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if y is None:
+            y = torch.empty(self.n_meas, dtype=torch.float32, device=x.device)
+        _check(lib().ltm_xport_project(self._h, _ptr(x, numel=self.n_voxels),
+                                       _ptr(y, numel=self.n_meas), _stream(stream)))
+        return y
+
+    def backproject(self, y: torch.Tensor, x: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if x is None:
+            x = torch.empty(self.n_voxels, dtype=torch.float32, device=y.device)
+        _check(lib().ltm_xport_backproject(self._h, _ptr(y, numel=self.n_meas),
+                                           _ptr(x, numel=self.n_voxels), _stream(stream)))
+        return x

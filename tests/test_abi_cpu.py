@@ -141,3 +141,31 @@ def test_hexagonal_camera_validation(L):
         if st:
             assert "3 x 3" in msg
     assert reach(W.hex_plenoptic_camera(2048)) < limit < reach(W.hex_plenoptic_camera(3000))
+
+
+def test_transport_operator_validation(L):
+    g = W.grid(24, 1.0)
+    ok = W.single_lens_camera(128, (4, 4), 8)
+    h = ctypes.c_void_p()
+    for basis in (0, 1):
+        assert L.lib().ltm_xport_create(ctypes.byref(L.make_grid(g)), L.make_cameras([ok]), basis,
+                                        ctypes.byref(h)) == 0
+        b = (ctypes.c_uint32 * 4)()
+        assert L.lib().ltm_xport_bands(h, b) == 0
+        assert all(1 <= v <= 64 for v in b)
+        n = ctypes.c_uint64()
+        assert L.lib().ltm_xport_workspace_bytes(h, ctypes.byref(n)) == 0
+        assert n.value >= 4 * 24 * 4 * 128 * 24                     # the filtering intermediate
+        # unbound: refuses to launch
+        assert L.lib().ltm_xport_project(h, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == \
+            L.LTM_ERR_WORKSPACE
+        L.lib().ltm_xport_destroy(h)
+    cases = [(W.single_lens_camera(128, (4, 4), 8, phi_deg=20.0), L.LTM_ERR_UNSUPPORTED, "head-on"),
+             (W.plenoptic_camera(64, 4, (2, 2), 8), L.LTM_ERR_UNSUPPORTED, "single-lens"),
+             (W.single_lens_camera(128, (4, 4), 8, distance=10.0), L.LTM_ERR_INVALID, "in front")]
+    for cam, status, needle in cases:
+        st = L.lib().ltm_xport_create(ctypes.byref(L.make_grid(g)), L.make_cameras([cam]), 1,
+                                      ctypes.byref(h))
+        assert st == status and needle in L.lib().ltm_last_error().decode()
+    assert L.lib().ltm_xport_create(ctypes.byref(L.make_grid(g)), L.make_cameras([ok]), 2,
+                                    ctypes.byref(h)) == L.LTM_ERR_INVALID
