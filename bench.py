@@ -331,6 +331,89 @@ def run_recon_three(args):
     return out
 
 
+def run_transport(args):
+    """The paper's own discretization (L2-projected light-field transport) at
+    the three-camera experiment's single-lens size: 1024^2 px of 5 um, 100^3
+    flame at 1 mm, 8x8 pillbox cells; one A x + one A^T y per step.  Then the
+    angular-discretization study: the normalized difference of Dirac and
+    pillbox images at K = 2^2 .. 32^2 from a Dirac 64^2 image, beside the
+    ray-driven operator (8x8 rays, 400 samples)."""
+    import numpy as np
+    import torch
+
+    from paper_1812_03358_amd import ltm, workloads as W
+
+    g = W.grid(100, 1.0)
+    cam = W.single_lens_camera(1024, (8, 8), 1)
+    x = torch.from_numpy(W.flame(100, 5).reshape(-1)).cuda()
+    t0 = time.perf_counter()
+    op = ltm.Transport(g, cam, ltm.BASIS_PILLBOX)
+    t_tables = time.perf_counter() - t0
+    y = op.project(x)
+    xt = torch.empty_like(x)
+    for _ in range(args.warmup):
+        op.project(x, y)
+        op.backproject(y, xt)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    f_ms = a_ms = 0.0
+    t_wall = time.perf_counter()
+    for _ in range(args.steps):
+        ev[0].record()
+        op.project(x, y)
+        ev[1].record()
+        op.backproject(y, xt)
+        ev[2].record()
+        torch.cuda.synchronize()
+        f_ms += ev[0].elapsed_time(ev[1])
+        a_ms += ev[1].elapsed_time(ev[2])
+    t_wall = time.perf_counter() - t_wall
+    f_ms /= args.steps
+    a_ms /= args.steps
+    ms = f_ms + a_ms
+    # algorithmic HBM bytes per direction: the FP32 intermediate written once
+    # and read once, the input read once, the output written once
+    mid = 100 * 8 * 1024 * 100 * 4
+    nbytes = 2 * mid + 4 * (100 ** 3 + 1024 ** 2)
+    out = base_record(args, 1000.0 / ms, ms,
+                      "transport_100: paper's L2-projected light-field transport, pillbox basis, "
+                      "single-lens 1024^2 head-on, 100^3 flame at 1 mm, 8x8 angular cells; one A x + "
+                      "one A^T y per step", {"bands": op.bands(), "table_build_s": round(t_tables, 3)})
+    out["metric"] = "transport A x + A^T y pairs/s"
+    out["unit"] = "pairs/s"
+    gbs = 2 * nbytes / (ms * 1e-3) / 1e9
+    out["roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
+    out["ms_project"] = round(f_ms, 4)
+    out["ms_backproject"] = round(a_ms, 4)
+    out["wall_s_timed"] = round(t_wall, 3)
+    # angular discretization study (no timing claims: each K builds its tables)
+    ref_op = ltm.Transport(g, W.single_lens_camera(1024, (64, 64), 1), ltm.BASIS_DIRAC)
+    ref = ref_op.project(x).double()
+    del ref_op
+    study = []
+    for basis, name in ((ltm.BASIS_DIRAC, "dirac"), (ltm.BASIS_PILLBOX, "pillbox")):
+        for K in (2, 4, 8, 16, 32):
+            o = ltm.Transport(g, W.single_lens_camera(1024, (K, K), 1), basis)
+            yk = o.project(x).double()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            o.project(x, None)
+            e1.record()
+            torch.cuda.synchronize()
+            study.append({"basis": name, "K": f"{K}x{K}",
+                          "nsd": float(torch.linalg.norm(yk - ref) / torch.linalg.norm(ref)),
+                          "ms_project": round(e0.elapsed_time(e1), 3)})
+            del o
+    plan = ltm.Plan(g, [W.single_lens_camera(1024, (8, 8), 400)])
+    yr = plan.project(x).double()
+    study.append({"basis": "ray-driven 8x8 rays, 400 samples", "K": "8x8",
+                  "nsd": float(torch.linalg.norm(yr - ref) / torch.linalg.norm(ref))})
+    out["angular_study_vs_dirac_64x64"] = study
+    return out
+
+
 def run_warm_start(args):
     """Learned warm start (2 plenoptic cameras at 0/90 deg, 128^3): train the
     network on projector-generated pairs for a time budget, then time the
@@ -378,7 +461,7 @@ def main():
     ap.add_argument("--workload", default="plenoptic_128",
                     choices=["plenoptic_128", "thin_lens_32", "differentiable_256", "batched_48",
                              "recon_plenoptic_128", "recon_three_camera_100", "warm_start_128",
-                             "hex_plenoptic_100"])
+                             "hex_plenoptic_100", "transport_100"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", action="store_true")
@@ -414,6 +497,8 @@ def main():
                          "array of 2.8/3.0/3.2 mm lenslets, light summed over all lenslets (3x3 "
                          "visited per pixel), 2x2 rays/lenslet, 200 samples/ray; one A x + one "
                          "A^T y per step")
+    elif args.workload == "transport_100":
+        out = run_transport(args)
     elif args.workload == "batched_48":
         out = run_batched(args)
     elif args.workload == "warm_start_128":

@@ -370,9 +370,9 @@ ltm_status ltm_nn_add(float* a, const float* b, uint64_t n, void* stream);
  * of the lens).  The volume is collapsed into its nz slices; slice iz at
  * camera depth z = distance + (iz + 1/2 - nz/2) pitch radiates the light
  * field dz * x[iz] for every angular cell.  The angular plane is the main
- * lens, divided into rays_u x rays_v square cells of size 2 r_main / rays_*
- * over its bounding square; cells whose centre lies outside the lens disc
- * are masked.  Each cell's transport is the Kronecker product of an s and a
+ * lens, divided into rays_u x rays_v cells (each 1..64) of size
+ * 2 r_main / rays_* over its bounding square; cells whose centre lies
+ * outside the lens disc are masked.  Each cell's transport is the Kronecker product of an s and a
  * t factor whose entries are the table's blur kernel integrated over the
  * source voxel; pixel i reads
  *   y_i = (dz / (K V^d)) sum_slices sum_cells [B_s (x) B_t] x_slice,

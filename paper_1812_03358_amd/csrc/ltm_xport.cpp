@@ -168,7 +168,12 @@ ltm_status ltm_xport_create(const ltm_grid* g, const ltm_camera* c, uint32_t bas
     if (!g || !c || !out) return fail(LTM_ERR_INVALID, "null argument");
     *out = nullptr;
     if (basis > LTM_BASIS_PILLBOX) return fail(LTM_ERR_INVALID, "basis must be Dirac or pillbox");
-    ltm_status st = validate_cameras(g, c, 1);
+    // the cell grid may be finer than the ray operator's R <= 64
+    if (c->rays_u == 0 || c->rays_v == 0 || c->rays_u > 64 || c->rays_v > 64)
+        return fail(LTM_ERR_INVALID, "need 1 <= rays_u, rays_v <= 64 angular cells");
+    ltm_camera one = *c;
+    one.rays_u = one.rays_v = 1;
+    ltm_status st = validate_cameras(g, &one, 1);
     if (st != LTM_OK) return st;
     if (c->kind != LTM_SINGLE_LENS)
         return fail(LTM_ERR_UNSUPPORTED, "the transport operator models single-lens cameras");
