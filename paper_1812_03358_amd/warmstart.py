@@ -61,8 +61,11 @@ def infer(net, plan, y, n, stream=None):
     return net.forward(inp, n, n, n, stream)
 
 
-def train(net, plan, n, seeds, lr=1e-3, time_limit=None, workers=8, log=None):
-    """One pass over the given seeds (or until time_limit seconds)."""
+def train(net, plan, n, seeds, lr=1e-3, time_limit=None, workers=8, log=None, warmup=100):
+    """One pass over the given seeds (or until time_limit seconds).  The
+    learning rate ramps linearly over the first `warmup` steps: Adam's first
+    steps move every weight by about lr at once, which at lr 1e-3 raises the
+    loss of the freshly initialized network several-fold."""
     stream = VolumeStream(n, seeds, workers)
     t0 = time.perf_counter()
     losses = []
@@ -74,7 +77,7 @@ def train(net, plan, n, seeds, lr=1e-3, time_limit=None, workers=8, log=None):
             out = infer(net, plan, y, n)
             loss, g = net.loss_and_grad(x)
             net.backward(g)
-            net.step(lr)
+            net.step(lr * min(1.0, (count + 1) / max(1, warmup)))
             count += 1
             if count % 25 == 0 or count == 1:
                 losses.append((count, float(loss)))

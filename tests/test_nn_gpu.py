@@ -257,8 +257,10 @@ def test_network_forward_backward_vs_float64(nn):
         worst = max(worst, e)
         assert e < 0.1, (name, e)
     print("worst layer weight-gradient rel error", worst, flush=True)
-    # one Adam step moves the loss down on this sample
-    net.step(lr=1e-3)
+    # one Adam step moves the loss down on this sample (at lr 1e-4: the first
+    # step moves every weight by about lr, and at 1e-3 it overshoots -- the
+    # float64 reference with torch.optim.Adam goes from 0.258 to 2.34 there)
+    net.step(lr=1e-4)
     net.forward(nn.to_bf16_tensor(x.reshape(-1)), n, n, n)
     loss2, _ = net.loss_and_grad(torch.from_numpy(target.reshape(-1)).cuda())
     assert float(loss2) < float(rl)
