@@ -7,6 +7,13 @@ exactly, up to FP64 rounding.  For a direction v supported on a 16^3
 sub-volume only the pixels whose rays cross it change, so the oracle loss is
 evaluated on those pixels alone (found from the oracle projection of the
 sub-volume's indicator, one voxel wider for the trilinear footprint).
+
+Each mismatch |fd - v.grad| is divided by ||A v|| ||r|| on those pixels
+(r = A x - y), the Cauchy-Schwarz bound of v.grad = <A v, r>.  The GPU
+gradient is built from the FP32 residual, whose error is about 1e-7 ||A x||
+per pixel; for a single-voxel direction whose positive and negative residual
+contributions cancel, v.grad itself can be far smaller than that error, so
+|v.grad| is not a usable scale there.
 """
 import numpy as np
 import pytest
@@ -66,10 +73,12 @@ def _fd_check(orc, ltm, autograd, g, cams, x, y, sub_lo, sub_n, n_dirs, n_vox, s
         v = np.zeros(n)
         v[tuple(sl + rng.integers(0, sub_n) for sl in sub_lo)] = 1.0
         dirs.append(v.reshape(-1))
+    r0 = np.concatenate(residuals(x64))
     for v in dirs:
         fd = loss_diff(x64 + h * v, x64 - h * v) / (2 * h)
         an = float(np.dot(grad, v))
-        scale = np.linalg.norm(grad[v != 0]) * np.linalg.norm(v[v != 0]) + 1e-30
+        Av = np.concatenate([orc.project_pixels(g, c, v, pix[k]) for k, c in enumerate(cams)])
+        scale = np.linalg.norm(Av) * np.linalg.norm(r0) + 1e-30
         errs.append(abs(fd - an) / scale)
     print("max FD mismatch", max(errs), flush=True)
     assert max(errs) < 1e-5
