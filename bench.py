@@ -102,6 +102,29 @@ def time_pair(plan, x, y, xt, steps, warmup):
     return total_ms / steps, fwd_ms, adj_ms, t_wall
 
 
+def counter_traffic(plan, direction):
+    """HBM bytes per launch of k_march from the committed FETCH_SIZE and
+    WRITE_SIZE summary, or None when the kernel source or the camera's default
+    tiling differs from the ones the counters were taken with."""
+    import hashlib
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        "k_march_plenoptic_128_hbm_counters.md")
+    try:
+        line = [l for l in open(path) if l.startswith("provenance: ")][0]
+        prov = json.loads(line[len("provenance: "):])
+        src = os.path.join(os.path.dirname(os.path.abspath(__file__)), prov["kernel_source"])
+        if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != prov["sha256_16"]:
+            return None
+        key = "tiling_forward" if direction == "project" else "tiling_adjoint"
+        t = plan.get_tiling(0 if direction == "project" else 1, 0)
+        if [t.tile_u, t.tile_v, t.order, t.splits, t.brick_floats] != prov[key]:
+            return None
+        return prov["traffic_bytes"][direction]
+    except (OSError, IndexError, KeyError, ValueError):
+        return None
+
+
 def roofline_of(valid, fwd_ms, adj_ms):
     dominant = "backproject" if adj_ms >= fwd_ms else "project"
     dom_ms = max(adj_ms, fwd_ms)
@@ -164,6 +187,9 @@ def run_single(args, cfg, workload):
     out = base_record(args, value, ms_step, workload,
                       {"valid_samples_per_direction": valid, "nominal_samples_per_direction": nominal})
     out["roofline"], out["gather_equivalent_hbm_frac"] = roofline_of(valid, fwd_ms, adj_ms)
+    if cfg["name"] == "plenoptic_128":
+        dom = "backproject" if adj_ms >= fwd_ms else "project"
+        out["roofline"]["traffic"] = counter_traffic(plan, dom)
     out["ms_project"] = round(fwd_ms, 4)
     out["ms_backproject"] = round(adj_ms, 4)
     out["gsamples_per_s_project"] = round(valid / (fwd_ms * 1e-3) / 1e9, 2)
