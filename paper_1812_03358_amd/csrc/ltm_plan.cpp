@@ -168,46 +168,60 @@ ltm_status check_tiling(const ltm_camera& c, const ltm_tiling& t)
 
 ltm_tiling default_tiling(const ltm_grid& g, const ltm_camera& c, int dir)
 {
+    // Defaults from tiling sweeps on MI355X (the autotuner refines them):
+    //  * forward: lanes of one lenslet / pixel block on adjacent lanes read
+    //    the same LDS words (a bundle is a fraction of a voxel wide); no
+    //    rotation of the starting angular sample; ~1-4k rays per group;
+    //  * adjoint: staggered sample walks and merged cells (bits 3, 4) break
+    //    the LDS atomic collisions of converging bundles; with many rays per
+    //    pixel, lanes also walk across lenslets / blocks (bit 0) and the slabs
+    //    get thinner.  The square-array plenoptic camera with R <= 4 keeps
+    //    4x4 lenslets and 256 pixels per group (fastest on the 128^3 case).
     ltm_tiling t{};
-    t.tile_u = t.tile_v = 1;
-    t.block_u = t.block_v = 16;
-    t.order = 0;
-    t.splits = 1;
-    t.brick_floats = 8192;
-    t.chunk_mm = 64.0 * g.pitch_mm;
     const uint64_t R = rays_per_pixel(c);
-    if (c.kind != LTM_PLENOPTIC)
-        while (t.block_u > 1 && (uint64_t)t.block_u * t.block_v * R > 4096u) {
-            t.block_u /= 2;
-            t.block_v /= 2;
-        }
-    if (c.kind == LTM_PLENOPTIC && dir == LTM_FORWARD) {
-        // a lenslet's rays with one aperture sample form a bundle a fraction
-        // of a voxel wide: lenslet-major lanes read the same LDS words
-        // (broadcast), and 2x2 lenslets split 4 ways keep 1024 rays per group
-        t.tile_u = t.tile_v = 2;
+    const bool pl = c.kind == LTM_PLENOPTIC;
+    const uint64_t k = pl ? (uint64_t)(c.det_nu / c.mla_nu) * (c.det_nv / c.mla_nv) : 0;
+    t.block_u = t.block_v = 16;
+    t.brick_floats = 8192;
+    if (dir == LTM_FORWARD) {
         t.order = 2;
-        t.splits = 4;
         t.brick_floats = 4096;
-    }
-    if (c.kind == LTM_PLENOPTIC && dir == LTM_ADJOINT) {
-        // staggered sample walks spread a lenslet's converging bundle over
-        // different voxels within a wave, and consecutive samples of one cell
-        // merge in registers before the LDS atomics: the fastest measured
-        // family on the 128^3 workload (4x4 lenslets, 256 pixels per group)
+        t.tile_u = t.tile_v = pl ? (R <= 4 ? 2 : 1) : 1;
+        t.chunk_mm = (c.kind == LTM_SINGLE_LENS ? 32.0 : 64.0) * g.pitch_mm;
+        const uint64_t items = (uint64_t)t.tile_u * t.tile_v * (pl ? k : 256);
+        const uint64_t target = R <= 4 ? 1024 : 4096;    // rays per group
+        t.splits = 1;
+        while (t.splits < items && items / t.splits * R > target) t.splits *= 2;
+    } else if (pl && R <= 4) {
         t.tile_u = t.tile_v = 4;
         t.order = 2 | 8 | 16;
         t.chunk_mm = 32.0 * g.pitch_mm;
-        const uint32_t k = (c.det_nu / c.mla_nu) * (c.det_nv / c.mla_nv);
-        t.splits = std::max(1u, 16u * k / 256u);    // 256 pixels per workgroup
-        while (t.splits > 1 && (16u * k) % t.splits) t.splits /= 2;
+        t.splits = (uint32_t)std::max<uint64_t>(1, 16 * k / 256);   // 256 pixels per group
+    } else {
+        t.tile_u = t.tile_v = 2;
+        t.block_u = t.block_v = 8;
+        t.order = (c.kind == LTM_PLENOPTIC_HEX ? 0 : 1) | 2 | 8 | 16;
+        t.chunk_mm = (c.kind == LTM_PLENOPTIC_HEX ? 32.0 : 16.0) * g.pitch_mm;
+        const uint64_t items = 4 * (pl ? k : 64);
+        t.splits = 1;
+        while (t.splits < items && items / t.splits * R > 4096) t.splits *= 2;
     }
-    // shrink until the ray list, pixel sums and brick fit one workgroup
+    // shrink until the ray list, pixel sums and brick fit one workgroup:
+    // too many rays or pixels per group -> more splits (the brick keeps its
+    // size: a smaller brick spills slabs to global memory); LDS overflow ->
+    // shrink the larger of the ray list (more splits) and the brick
+    const uint64_t ku = c.kind == LTM_PLENOPTIC ? c.det_nu / c.mla_nu : t.block_u;
+    const uint64_t kv = c.kind == LTM_PLENOPTIC ? c.det_nv / c.mla_nv : t.block_v;
+    const uint64_t items = (uint64_t)t.tile_u * t.tile_v * ku * kv;
     for (int guard = 0; guard < 64 && check_tiling(c, t) != LTM_OK; ++guard) {
-        if (t.brick_floats > 2048)
-            t.brick_floats /= 2;
-        else
+        const uint64_t per = (items + t.splits - 1) / t.splits;
+        if (per > 8ull * kThreads || per * R > (uint64_t)kMaxRayList) {
             t.splits *= 2;
+        } else if (per * R >= t.brick_floats && per > 1) {
+            t.splits *= 2;
+        } else {
+            t.brick_floats /= 2;
+        }
     }
     clear_error();
     return t;
