@@ -351,7 +351,7 @@ ltm_status ltm_nn_upsample2_backward(const float* d_high, float* d_low, uint32_t
 /* g = d_out * (out > 0) (or d_out when relu = 0) as BF16; d_bias += per-channel sums (may be NULL). */
 ltm_status ltm_nn_relu_backward(const float* d_out, const uint16_t* out, uint32_t relu, uint16_t* g,
                                 float* d_bias, uint64_t n, uint32_t c, void* stream);
-/* loss += mean((x - target)^2) (FP64 scalar), grad = its gradient through a final ReLU. */
+/* loss += mean((x - target)^2) (FP64 scalar), grad = 2 (x - target) / n. */
 ltm_status ltm_nn_mse(const float* x, const float* target, float* grad, double* loss, uint64_t n,
                       void* stream);
 /* One bias-corrected Adam step (step >= 1) on FP32 weights; g is cleared. */

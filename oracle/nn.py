@@ -100,7 +100,7 @@ ARCH = [
     ("u1", ("d22",), 32, 0, 16, 3, True, True),
     ("d11", ("u1", "e12"), 16, 16, 16, 3, False, True),
     ("d12", ("d11",), 16, 0, 16, 3, False, True),
-    ("out", ("d12",), 16, 0, 1, 1, False, True),
+    ("out", ("d12",), 16, 0, 1, 1, False, False),
 ]
 POOLS = {"p1": "e12", "p2": "e22", "p3": "e32"}
 

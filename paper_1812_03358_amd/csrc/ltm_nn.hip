@@ -320,7 +320,7 @@ __global__ void k_mse(const float* __restrict__ x, const float* __restrict__ t, 
         const double dd = (double)x[i] - (double)t[i];   // exact for FP32 inputs
         s += dd * dd;
         const float d = x[i] - t[i];
-        g[i] = x[i] > 0.0f ? 2.0f * d * inv : 0.0f;
+        g[i] = 2.0f * d * inv;
     }
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;

@@ -154,8 +154,12 @@ class UNet:
         _ltm._check(_lib().ltm_nn_prep_input(_p(aty), _p(out), _p(self._scratch), aty.numel(), _s(stream)))
         return out
 
-    def forward(self, x_in: torch.Tensor, D: int, H: int, W: int, stream=None) -> torch.Tensor:
-        """x_in: BF16 bits [D*H*W] (one channel).  Returns the FP32 volume."""
+    def forward(self, x_in: torch.Tensor, D: int, H: int, W: int, stream=None,
+                final_relu: bool = False) -> torch.Tensor:
+        """x_in: BF16 bits [D*H*W] (one channel).  Returns the FP32 volume.
+        The output layer is linear in training (a ReLU there leaves a freshly
+        initialized network with almost no positive outputs, hence no
+        gradient); inference passes final_relu=True for a nonnegative x0."""
         lib = _lib()
         A = {"in": x_in}
         for name in ORDER:
@@ -174,7 +178,8 @@ class UNet:
             last = name == "out"
             out = torch.empty(d * h * w * L.cout, dtype=torch.float32 if last else torch.int16,
                               device=self.device)
-            desc = conv_desc(L.ks, d, h, w, L.c0, L.c1, L.cout, L.up, 1, int(last))
+            desc = conv_desc(L.ks, d, h, w, L.c0, L.c1, L.cout, L.up,
+                             int(final_relu) if last else 1, int(last))
             in1 = A[L.ins[1]] if len(L.ins) > 1 else None
             _ltm._check(lib.ltm_nn_conv3d_forward(ctypes.byref(desc), _p(A[L.ins[0]]), _p(in1), _p(L.wf),
                                                   _p(L.b), _p(out), None, _s(stream)))
@@ -192,8 +197,8 @@ class UNet:
         return self._loss, g
 
     def backward(self, g_out: torch.Tensor, stream=None):
-        """Accumulate dw, db from d loss / d out (FP32, already through the
-        final ReLU, as ltm_nn_mse returns it)."""
+        """Accumulate dw, db from d loss / d out (FP32, the linear output's
+        gradient as ltm_nn_mse returns it)."""
         lib = _lib()
         D, H, W = self.dims
         A = self.acts

@@ -54,11 +54,11 @@ def make_plan(device="cuda"):
     return _ltm.Plan(cfg["grid"], cfg["cameras"], device=device), cfg
 
 
-def infer(net, plan, y, n, stream=None):
+def infer(net, plan, y, n, stream=None, final_relu=True):
     """Network estimate of the volume from images y (FP32 on the device)."""
     aty = plan.backproject(y)
     inp = net.prep_input(aty, stream)
-    return net.forward(inp, n, n, n, stream)
+    return net.forward(inp, n, n, n, stream, final_relu=final_relu)
 
 
 def train(net, plan, n, seeds, lr=1e-3, time_limit=None, workers=8, log=None, warmup=100):
@@ -74,7 +74,7 @@ def train(net, plan, n, seeds, lr=1e-3, time_limit=None, workers=8, log=None, wa
         for seed, vol in stream:
             x = torch.from_numpy(vol.reshape(-1)).to(net.device)
             y = plan.project(x)
-            out = infer(net, plan, y, n)
+            infer(net, plan, y, n, final_relu=False)      # the loss sees the linear output
             loss, g = net.loss_and_grad(x)
             net.backward(g)
             net.step(lr * min(1.0, (count + 1) / max(1, warmup)))

@@ -53,12 +53,15 @@ def test_pool_and_upsample_match_torch():
     assert np.array_equal(onn.upsample2(x), up)
 
 
-def test_unet_shapes_and_positivity():
+def test_unet_shapes_and_linear_output():
     rng = np.random.default_rng(1)
     params = {}
     for name, _, c0, c1, cout, ks, _, _ in onn.ARCH:
         fan = ks ** 3 * (c0 + c1)
         params[name] = (rng.standard_normal((cout, fan)) * np.sqrt(2.0 / fan), np.zeros(cout))
     out, acts = onn.unet_forward(params, rng.uniform(0, 1, (8, 8, 8, 1)))
-    assert out.shape == (8, 8, 8) and out.min() >= 0.0
+    # the output layer is linear (its ReLU applies only at inference) ...
+    assert out.shape == (8, 8, 8) and out.min() < 0.0 < out.max()
+    # ... and every hidden activation passed its ReLU
+    assert all(acts[k].min() >= 0.0 for k in acts if k not in ("in", "out"))
     assert acts["e42"].shape == (1, 1, 1, 128)
