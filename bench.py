@@ -424,6 +424,8 @@ def run_transport(args):
     out["ms_project"] = round(f_ms, 4)
     out["ms_backproject"] = round(a_ms, 4)
     out["wall_s_timed"] = round(t_wall, 3)
+    if args.no_study:
+        return out
     # angular discretization study (no timing claims: each K builds its tables)
     ref_op = ltm.Transport(g, W.single_lens_camera(1024, (64, 64), 1), ltm.BASIS_DIRAC)
     ref = ref_op.project(x).double()
@@ -509,6 +511,7 @@ def main():
     ap.add_argument("--eval-volumes", type=int, default=4)
     ap.add_argument("--max-iter", type=int, default=4000)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--no-study", action="store_true", help="transport_100: skip the angular study")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "

@@ -8,8 +8,7 @@
 // (the cells of one angular row share their t factor).  The adjoint runs the
 // transposed tables in the opposite order.  Every output has one writer
 // (no atomics): the minor passes write one intermediate value per thread and
-// the major passes accumulate a whole output in FP64 registers (the handful
-// of band terms of one (slice, angular row) pair in FP32 first).
+// the major passes accumulate a whole output in FP64 registers.
 #include "ltm_xport.h"
 
 namespace ltm {
@@ -42,8 +41,7 @@ __global__ __launch_bounds__(kBlock) void k_minor_fwd(XportDev d, const float* _
     }
 }
 
-// y[v][u] for kRowsPerThread consecutive rows v of one column u; the few
-// terms of one (slice, row) pair add in FP32, the pairs in FP64.
+// y[v][u] for kRowsPerThread consecutive rows v of one column u.
 __global__ __launch_bounds__(kBlock) void k_major_fwd(XportDev d, float* __restrict__ y)
 {
     const int vblocks = (d.nv + kRowsPerThread - 1) / kRowsPerThread;
@@ -60,19 +58,14 @@ __global__ __launch_bounds__(kBlock) void k_major_fwd(XportDev d, float* __restr
             const int st = d.cs.start[p * d.nu + u];
             const float* w = d.cs.w + p * d.cs.width * (size_t)d.nu + u;
             const float* m = d.mid + p * d.nv * (size_t)d.nx;
-            float part[kRowsPerThread];
-#pragma unroll
-            for (int r = 0; r < kRowsPerThread; ++r) part[r] = 0.0f;
             for (int k = 0; k < d.cs.width; ++k) {
                 const int ix = st + k;
                 if (ix >= d.nx) break;
                 const float c = w[(size_t)k * d.nu];
 #pragma unroll
                 for (int r = 0; r < kRowsPerThread; ++r)
-                    if (v0 + r < d.nv) part[r] = fmaf(c, m[(size_t)(v0 + r) * d.nx + ix], part[r]);
+                    if (v0 + r < d.nv) acc[r] += (double)(c * m[(size_t)(v0 + r) * d.nx + ix]);
             }
-#pragma unroll
-            for (int r = 0; r < kRowsPerThread; ++r) acc[r] += (double)part[r];
         }
 #pragma unroll
         for (int r = 0; r < kRowsPerThread; ++r)
