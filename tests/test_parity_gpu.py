@@ -185,3 +185,25 @@ def test_valid_ray_counts_match_oracle(orc, ltm, which):
             gpu, ref = plan.valid_rays(k), orc.count_valid_rays(g, c)
             print(which, g["nx"], k, gpu, ref, flush=True)
             assert gpu == ref
+
+
+def test_differentiable_256_sampled_pixels(orc, ltm):
+    # the 256^3 four-camera workload at full size, in the tiling the bench
+    # times: sampled pixels of every camera against the oracle's pixels
+    cfg = W.config_differentiable()
+    g, cams = cfg["grid"], cfg["cameras"]
+    x = cfg["volume"]()
+    plan = ltm.Plan(g, cams)
+    Ax = plan.project(torch.from_numpy(x.reshape(-1)).cuda()).cpu().numpy()
+    x64 = x.astype(np.float64).reshape(-1)
+    rng = np.random.default_rng(21)
+    off = 0
+    for k, c in enumerate(cams):
+        npx = c["det_nu"] * c["det_nv"]
+        pix = np.unique(np.concatenate([rng.integers(0, npx, 1500), [0, npx - 1, npx // 2 + c["det_nu"] // 2]]))
+        ref = orc.project_pixels(g, c, x64, pix)
+        e = rel_l2(Ax[off + pix], ref)
+        print(f"camera {k}: sampled rel L2 {e:.2e}", flush=True)
+        assert np.count_nonzero(ref) > 100
+        assert e < TOL
+        off += npx
