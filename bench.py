@@ -129,7 +129,7 @@ def counter_traffic(plan, direction):
             return None
         key = "tiling_forward" if direction == "project" else "tiling_adjoint"
         t = plan.get_tiling(0 if direction == "project" else 1, 0)
-        if [t.tile_u, t.tile_v, t.order, t.splits, t.brick_floats] != prov[key]:
+        if [t.tile_u, t.tile_v, t.order, t.splits, t.brick_floats, round(t.chunk_mm, 6)] != prov[key]:
             return None
         return prov["traffic_bytes"][direction]
     except (OSError, IndexError, KeyError, ValueError):

@@ -155,7 +155,12 @@ ltm_status ltm_plan_workspace_bytes(const ltm_plan* plan, uint64_t* bytes);
 
 /* Bind a caller-owned device workspace and fill its tables on `stream`.  The
  * workspace must stay valid while the plan is used.  Must be called before
- * ltm_project / ltm_backproject, and again after ltm_plan_set_tiling. */
+ * ltm_project / ltm_backproject, and again after ltm_plan_set_tiling.
+ * Cameras on their default tilings adapt the slab depth here: while more
+ * than 1% of a tiling's slabs have voxel boxes too large for LDS, the slab
+ * depth halves (at most three times; ltm_plan_get_tiling reports the
+ * result), which reads the tables back and synchronizes `stream`.
+ * Tilings set with ltm_plan_set_tiling are used as given. */
 ltm_status ltm_plan_bind_workspace(ltm_plan* plan, void* ws, uint64_t bytes, void* stream);
 
 ltm_status ltm_plan_get_tiling(const ltm_plan* plan, uint32_t direction, uint32_t camera,

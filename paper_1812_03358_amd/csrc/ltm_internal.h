@@ -104,6 +104,10 @@ struct CamHost {
     // workspace offsets (bytes) of this camera's tables, per direction
     uint64_t tiles_off[2], bricks_off[2];
     int n_tiles[2], max_chunks[2];
+    // default tilings adapt their slab depth at bind time (down to
+    // chunk_floor, which sizes the brick table); explicit tilings do not
+    bool adapt[2];
+    double chunk_floor[2];
 };
 
 }  // namespace ltm

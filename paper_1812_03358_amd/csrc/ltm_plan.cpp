@@ -297,7 +297,7 @@ void camera_constants(const ltm_grid& g, const ltm_camera& c, CamDev& d)
 
 // Tiling-dependent fields.
 void apply_tiling(const ltm_grid& g, const ltm_camera& c, const ltm_tiling& t, CamDev& d,
-                  int& n_tiles, int& max_chunks)
+                  int& n_tiles, int& max_chunks, double chunk_floor)
 {
     if (c.kind == LTM_PLENOPTIC) {
         d.ku = (int)(c.det_nu / c.mla_nu);
@@ -327,7 +327,7 @@ void apply_tiling(const ltm_grid& g, const ltm_camera& c, const ltm_tiling& t, C
     d.chunk = (float)t.chunk_mm;
     const double diag = g.pitch_mm * std::sqrt((double)g.nx * g.nx + (double)g.ny * g.ny +
                                                (double)g.nz * g.nz);
-    d.max_chunks = (int)std::ceil(diag / t.chunk_mm) + 2;
+    d.max_chunks = (int)std::ceil(diag / std::min(chunk_floor, t.chunk_mm)) + 2;
     n_tiles = d.n_tiles;
     max_chunks = d.max_chunks;
 }
@@ -338,7 +338,8 @@ void layout(ltm_plan* p)
     for (auto& c : p->cams) {
         for (int dir = 0; dir < 2; ++dir) {
             CamDev tmp = c.dev;
-            apply_tiling(p->grid, c.desc, c.tiling[dir], tmp, c.n_tiles[dir], c.max_chunks[dir]);
+            apply_tiling(p->grid, c.desc, c.tiling[dir], tmp, c.n_tiles[dir], c.max_chunks[dir],
+                         c.chunk_floor[dir]);
             c.tiles_off[dir] = off;
             off = align256(off + sizeof(TileRec) * (uint64_t)c.n_tiles[dir]);
             c.bricks_off[dir] = off;
@@ -377,7 +378,7 @@ CamDev bound_dev(const ltm_plan* p, const CamHost& c, int dir)
 {
     CamDev d = c.dev;
     int nt, mc;
-    apply_tiling(p->grid, c.desc, c.tiling[dir], d, nt, mc);
+    apply_tiling(p->grid, c.desc, c.tiling[dir], d, nt, mc, c.chunk_floor[dir]);
     if (dir == LTM_ADJOINT && !d.adj_f32) d.brick_cap /= 2;   // FP64 brick in the same LDS budget
     if (p->sub_n > 1) {
         // mean over the subset's samples: the view-subset operator (K/|S|) A_S
@@ -424,7 +425,11 @@ ltm_status ltm_plan_create(const ltm_grid* grid, const ltm_camera* cams, uint32_
     for (uint32_t i = 0; i < n_cam; ++i) {
         CamHost c{};
         c.desc = cams[i];
-        for (int dir = 0; dir < 2; ++dir) c.tiling[dir] = default_tiling(*grid, cams[i], dir);
+        for (int dir = 0; dir < 2; ++dir) {
+            c.tiling[dir] = default_tiling(*grid, cams[i], dir);
+            c.adapt[dir] = true;
+            c.chunk_floor[dir] = c.tiling[dir].chunk_mm / 8.0;
+        }
         camera_constants(*grid, cams[i], c.dev);
         c.npix = (uint64_t)cams[i].det_nu * cams[i].det_nv;
         c.y_off = yoff;
@@ -465,11 +470,36 @@ ltm_status ltm_plan_bind_workspace(ltm_plan* p, void* ws, uint64_t bytes, void* 
         return fail(LTM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
     p->ws = static_cast<char*>(ws);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<TileRec> tiles;
+    std::vector<BrickRec> bricks;
     for (auto& c : p->cams)
         for (int dir = 0; dir < 2; ++dir) {
-            const CamDev d = bound_dev(p, c, dir);
-            hipError_t e = launch_setup(d, dir, s);
-            if (e != hipSuccess) return hip_fail(e, "tile setup");
+            for (;;) {
+                const CamDev d = bound_dev(p, c, dir);
+                hipError_t e = launch_setup(d, dir, s);
+                if (e != hipSuccess) return hip_fail(e, "tile setup");
+                if (!c.adapt[dir] || c.tiling[dir].chunk_mm * 0.5 < c.chunk_floor[dir] * 0.999) break;
+                // default tilings: halve the slab depth while more than 1% of the
+                // used slabs have voxel boxes too large for LDS (global memory is
+                // many times slower, oblique poses need thinner slabs)
+                tiles.resize(d.n_tiles);
+                bricks.resize((size_t)d.n_tiles * d.max_chunks);
+                e = hipMemcpyAsync(tiles.data(), d.tiles, tiles.size() * sizeof(TileRec),
+                                   hipMemcpyDeviceToHost, s);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(bricks.data(), d.bricks, bricks.size() * sizeof(BrickRec),
+                                       hipMemcpyDeviceToHost, s);
+                if (e == hipSuccess) e = hipStreamSynchronize(s);
+                if (e != hipSuccess) return hip_fail(e, "tile setup readback");
+                uint64_t used = 0, spill = 0;
+                for (int t = 0; t < d.n_tiles; ++t)
+                    for (int ch = 0; ch < tiles[t].n_chunks; ++ch) {
+                        ++used;
+                        spill += bricks[(size_t)t * d.max_chunks + ch].lds ? 0 : 1;
+                    }
+                if (spill * 100 <= used) break;
+                c.tiling[dir].chunk_mm *= 0.5;
+            }
         }
     p->bound = true;
     clear_error();
@@ -491,6 +521,8 @@ ltm_status ltm_plan_set_tiling(ltm_plan* p, uint32_t dir, uint32_t cam, const lt
     ltm_status s = check_tiling(p->cams[cam].desc, *t);
     if (s != LTM_OK) return s;
     p->cams[cam].tiling[dir] = *t;
+    p->cams[cam].adapt[dir] = false;
+    p->cams[cam].chunk_floor[dir] = t->chunk_mm;
     layout(p);
     p->bound = false;
     p->ws = nullptr;
