@@ -73,6 +73,65 @@ __global__ __launch_bounds__(kBlock) void k_major_fwd(XportDev d, float* __restr
     }
 }
 
+// Same as k_major_fwd (one row per thread) with the band width fixed at
+// compile time: the padded weights are zero, so the column index is clamped
+// instead of tested, and the pair loop unrolls so that the independent table
+// and intermediate loads of several pairs are in flight together.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_major_fwd_w(XportDev d, float* __restrict__ y)
+{
+    const size_t total = (size_t)d.nv * d.nu;
+    const size_t pairs = (size_t)d.nz * d.kt;
+    const size_t pstride = (size_t)d.nv * d.nx;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * kBlock) {
+        const int u = (int)(i % d.nu);
+        const int v = (int)(i / d.nu);
+        const float* mrow = d.mid + (size_t)v * d.nx;
+        double acc = 0.0;
+#pragma unroll 4
+        for (size_t p = 0; p < pairs; ++p) {
+            const int st = d.cs.start[p * d.nu + u];
+            const float* w = d.cs.w + p * W * (size_t)d.nu + u;
+            const float* m = mrow + p * pstride;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const int ix = min(st + k, d.nx - 1);
+                acc += (double)(w[(size_t)k * d.nu] * m[ix]);
+            }
+        }
+        y[i] = (float)acc;
+    }
+}
+
+// Same as k_major_adj with the loop bound fixed at compile time (W >= the
+// table's width; the terms past the width are skipped).
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_major_adj_w(XportDev d, const float* __restrict__ y)
+{
+    const size_t total = (size_t)d.nz * d.kt * d.nv * d.nx;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * kBlock) {
+        const int ix = (int)(i % d.nx);
+        const size_t r = i / d.nx;
+        const int v = (int)(r % d.nv);
+        const size_t p = r / d.nv;
+        const int wd = d.cst.width;
+        const int st = d.cst.start[p * d.nx + ix];
+        const float* w = d.cst.w + p * wd * (size_t)d.nx + ix;
+        const float* yr = y + (size_t)v * d.nu;
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            if (k < wd) {
+                const int u = min(st + k, d.nu - 1);
+                acc += (double)(w[(size_t)k * d.nx] * yr[u]);
+            }
+        }
+        d.mid[i] = (float)acc;
+    }
+}
+
 // M[p][v][ix] = sum_k cst.w[p][k][ix] * y[v][start + k]
 __global__ __launch_bounds__(kBlock) void k_major_adj(XportDev d, const float* __restrict__ y)
 {
@@ -135,14 +194,29 @@ hipError_t launch_xport_project(const XportDev& d, const float* x, float* y, hip
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t ny = (size_t)((d.nv + kRowsPerThread - 1) / kRowsPerThread) * d.nu;
-    hipLaunchKernelGGL(k_major_fwd, dim3(grid_for(ny)), dim3(kBlock), 0, s, d, y);
+    const dim3 g(grid_for(ny)), b(kBlock);
+    switch (d.cs.width) {
+    case 1: hipLaunchKernelGGL(k_major_fwd_w<1>, g, b, 0, s, d, y); break;
+    case 2: hipLaunchKernelGGL(k_major_fwd_w<2>, g, b, 0, s, d, y); break;
+    case 3: hipLaunchKernelGGL(k_major_fwd_w<3>, g, b, 0, s, d, y); break;
+    case 4: hipLaunchKernelGGL(k_major_fwd_w<4>, g, b, 0, s, d, y); break;
+    default: hipLaunchKernelGGL(k_major_fwd, g, b, 0, s, d, y); break;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_xport_backproject(const XportDev& d, const float* y, float* x, hipStream_t s)
 {
     const size_t nm = (size_t)d.nz * d.kt * d.nv * d.nx;
-    hipLaunchKernelGGL(k_major_adj, dim3(grid_for(nm)), dim3(kBlock), 0, s, d, y);
+    const dim3 g(grid_for(nm)), b(kBlock);
+    if (d.cst.width <= 8)
+        hipLaunchKernelGGL(k_major_adj_w<8>, g, b, 0, s, d, y);
+    else if (d.cst.width <= 16)
+        hipLaunchKernelGGL(k_major_adj_w<16>, g, b, 0, s, d, y);
+    else if (d.cst.width <= 24)
+        hipLaunchKernelGGL(k_major_adj_w<24>, g, b, 0, s, d, y);
+    else
+        hipLaunchKernelGGL(k_major_adj, g, b, 0, s, d, y);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t nx = (size_t)d.nz * d.ny * d.nx;
