@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 #   adjoint: position (6), fraction (3), 3 complements, 2 + 4 + 8
 #            weight products (17), 8 additions into the voxels (8)    -> 34
 FLOP_PER_SAMPLE = {"project": 31.0, "backproject": 34.0}
-# FP32 vector peak without packed-FP32 dual issue (disabled in this build):
+# FP32 vector peak without packed-FP32 dual issue (the kernels are compiled without it):
 # 256 CUs x 4 SIMD x 16 lanes x 2 flop/FMA x 2.4 GHz
 PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
