@@ -9,6 +9,8 @@
 // transposed tables in the opposite order.  Every output has one writer
 // (no atomics): the minor passes write one intermediate value per thread and
 // the major passes accumulate a whole output in FP64 registers.
+#include <algorithm>
+
 #include "ltm_xport.h"
 
 namespace ltm {
@@ -132,6 +134,49 @@ __global__ __launch_bounds__(kBlock) void k_major_adj_w(XportDev d, const float*
     }
 }
 
+// Adjoint major pass with the image rows staged in LDS: a workgroup takes
+// `rows` detector rows (staged once, coalesced) and a chunk of (slice, row)
+// pairs; a thread holds one (pair, voxel column)'s band weights in registers
+// and applies them to every staged row.  The image gathers hit LDS instead
+// of scattered global loads.  W >= the table's width (terms past it skipped).
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_major_adj_lds(XportDev d, const float* __restrict__ y,
+                                                          int rows, int pchunk)
+{
+    extern __shared__ float ys[];
+    const int v0 = blockIdx.x * rows;
+    const int nr = min(rows, d.nv - v0);
+    for (int i = threadIdx.x; i < nr * d.nu; i += kBlock) ys[i] = y[(size_t)v0 * d.nu + i];
+    __syncthreads();
+    const size_t pairs = (size_t)d.nz * d.kt;
+    const size_t pb = (size_t)blockIdx.y * pchunk;
+    const size_t pe = pb + pchunk < pairs ? pb + pchunk : pairs;
+    const int wd = d.cst.width;
+    const size_t items = (pe - pb) * d.nx;
+    for (size_t it = threadIdx.x; it < items; it += kBlock) {
+        const size_t p = pb + it / d.nx;
+        const int ix = (int)(it % d.nx);
+        const int st = d.cst.start[p * d.nx + ix];
+        const float* wp = d.cst.w + p * wd * (size_t)d.nx + ix;
+        float w[W];
+        int col[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            w[k] = k < wd ? wp[(size_t)k * d.nx] : 0.0f;
+            col[k] = min(st + k, d.nu - 1);
+        }
+        float* out = d.mid + (p * d.nv + v0) * (size_t)d.nx + ix;
+        for (int r = 0; r < nr; ++r) {
+            const float* yr = ys + r * d.nu;
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < W; ++k)
+                if (k < wd) acc += (double)(w[k] * yr[col[k]]);
+            out[(size_t)r * d.nx] = (float)acc;
+        }
+    }
+}
+
 // M[p][v][ix] = sum_k cst.w[p][k][ix] * y[v][start + k]
 __global__ __launch_bounds__(kBlock) void k_major_adj(XportDev d, const float* __restrict__ y)
 {
@@ -209,10 +254,18 @@ hipError_t launch_xport_backproject(const XportDev& d, const float* y, float* x,
 {
     const size_t nm = (size_t)d.nz * d.kt * d.nv * d.nx;
     const dim3 g(grid_for(nm)), b(kBlock);
-    if (d.cst.width <= 8)
-        hipLaunchKernelGGL(k_major_adj_w<8>, g, b, 0, s, d, y);
-    else if (d.cst.width <= 16)
-        hipLaunchKernelGGL(k_major_adj_w<16>, g, b, 0, s, d, y);
+    const int rows = std::min(16, 16384 / std::max(1, d.nu));     // <= 64 KiB of staged rows
+    const size_t pairs = (size_t)d.nz * d.kt;
+    const int pchunk = 32;
+    const dim3 gl((unsigned)((d.nv + rows - 1) / std::max(1, rows)),
+                  (unsigned)((pairs + pchunk - 1) / pchunk));
+    const size_t lds = (size_t)std::max(1, rows) * d.nu * sizeof(float);
+    if (rows >= 1 && gl.y < 65536 && d.cst.width <= 8)
+        hipLaunchKernelGGL(k_major_adj_lds<8>, gl, b, lds, s, d, y, rows, pchunk);
+    else if (rows >= 1 && gl.y < 65536 && d.cst.width <= 16)
+        hipLaunchKernelGGL(k_major_adj_lds<16>, gl, b, lds, s, d, y, rows, pchunk);
+    else if (rows >= 1 && gl.y < 65536 && d.cst.width <= 24)
+        hipLaunchKernelGGL(k_major_adj_lds<24>, gl, b, lds, s, d, y, rows, pchunk);
     else if (d.cst.width <= 24)
         hipLaunchKernelGGL(k_major_adj_w<24>, g, b, 0, s, d, y);
     else
