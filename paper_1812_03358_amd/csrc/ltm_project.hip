@@ -182,6 +182,23 @@ __device__ __forceinline__ Cell cell_of(float qx, float qy, float qz, const Boun
     return s;
 }
 
+// The same trilinear cell inside an LDS brick that carries one replicated
+// layer outside the grid on every side (index -1 holds voxel 0, index n holds
+// voxel n-1): the clamps drop out.  For q in the outer half-voxel shell the
+// interpolation mixes a voxel with its own copy, a + f (a - a) = a exactly,
+// which is the clamped value; inside it is the same cell as cell_of.
+__device__ __forceinline__ Cell cell_of_padded(float qx, float qy, float qz)
+{
+    Cell s;
+    const float q[3] = {qx, qy, qz};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        s.i[k] = floorf(q[k]);
+        s.f[k] = q[k] - s.i[k];
+    }
+    return s;
+}
+
 __device__ __forceinline__ float lerp(float a, float b, float t) { return fmaf(t, b - a, a); }
 
 __device__ __forceinline__ float tri(float c000, float c100, float c010, float c110, float c001,
@@ -283,9 +300,9 @@ __global__ __launch_bounds__(kThreads) void k_setup(CamDev c, TileRec* tiles, Br
             const float h = block_reduce(hi[k], true, red);
             int il = 0, ih = 1;
             if (h >= l) {
-                il = max(0, (int)floorf(l) - 1);
-                ih = min(c.n[k] - 1, (int)floorf(h) + 2);
-                il = min(il, c.n[k] - 2);
+                // one replicated layer past the grid on each side (-1 .. n)
+                il = max(-1, (int)floorf(l) - 1);
+                ih = min(c.n[k], (int)floorf(h) + 2);
                 ih = max(ih, il + 1);
             }
             br.lo[k] = il;
@@ -314,6 +331,13 @@ __device__ __forceinline__ size_t gindex(const int n[3], int x, int y, int z)
     return (size_t)x + (size_t)n[0] * ((size_t)y + (size_t)n[1] * (size_t)z);
 }
 
+// Grid index of a brick voxel, whose coordinates may lie one past the grid:
+// the replicated layer maps onto the edge voxel.
+__device__ __forceinline__ size_t gindex_clamped(const int n[3], int x, int y, int z)
+{
+    return gindex(n, min(max(x, 0), n[0] - 1), min(max(y, 0), n[1] - 1), min(max(z, 0), n[2] - 1));
+}
+
 __device__ void stage_brick(const BrickRec& b, const int n[3], const float* __restrict__ x,
                             float* brick)
 {
@@ -322,7 +346,7 @@ __device__ void stage_brick(const BrickRec& b, const int n[3], const float* __re
     for (int e = threadIdx.x; e < vol; e += kThreads) {
         int lx, ly, lz;
         brick_coords(e, b.dim[0], b.dim[1], idx, idy, lx, ly, lz);
-        brick[e] = x[gindex(n, b.lo[0] + lx, b.lo[1] + ly, b.lo[2] + lz)];
+        brick[e] = x[gindex_clamped(n, b.lo[0] + lx, b.lo[1] + ly, b.lo[2] + lz)];
     }
 }
 
@@ -343,7 +367,7 @@ __device__ void flush_brick(const BrickRec& b, const int n[3], T* brick, double*
         if (v == 0.0) continue;
         int lx, ly, lz;
         brick_coords(e, b.dim[0], b.dim[1], idx, idy, lx, ly, lz);
-        unsafeAtomicAdd(&x[gindex(n, b.lo[0] + lx, b.lo[1] + ly, b.lo[2] + lz)], v);
+        unsafeAtomicAdd(&x[gindex_clamped(n, b.lo[0] + lx, b.lo[1] + ly, b.lo[2] + lz)], v);
     }
 }
 
@@ -376,8 +400,8 @@ __device__ __forceinline__ double gather_lds(const March& mr, int m0, int m1, co
         const float fend = (float)min(g0 + 8, m1);
         float part = 0.0f;
         for (float fm = (float)g0; fm < fend; fm += 1.0f) {
-            const Cell s = cell_of(fmaf(fm, mr.st[0], mr.qs[0]), fmaf(fm, mr.st[1], mr.qs[1]),
-                                   fmaf(fm, mr.st[2], mr.qs[2]), bd);
+            const Cell s = cell_of_padded(fmaf(fm, mr.st[0], mr.qs[0]), fmaf(fm, mr.st[1], mr.qs[1]),
+                                   fmaf(fm, mr.st[2], mr.qs[2]));
             const float fi = fmaf(s.i[2], dxy, fmaf(s.i[1], dx, s.i[0])) - b.base;
             const int i0 = (int)clampf(fi, 0.0f, maxi);
             const float* p = brick + i0;
@@ -440,8 +464,8 @@ __device__ __forceinline__ void scatter_lds(const March& mr, int m0, int m1, con
     if (skew) m += (int)(((threadIdx.x & 63) * (unsigned)cnt) >> 6);
     for (int k = 0; k < cnt; ++k) {
         const float fm = (float)m;
-        const Cell s = cell_of(fmaf(fm, mr.st[0], mr.qs[0]), fmaf(fm, mr.st[1], mr.qs[1]),
-                               fmaf(fm, mr.st[2], mr.qs[2]), bd);
+        const Cell s = cell_of_padded(fmaf(fm, mr.st[0], mr.qs[0]), fmaf(fm, mr.st[1], mr.qs[1]),
+                               fmaf(fm, mr.st[2], mr.qs[2]));
         const float fi = fmaf(s.i[2], dxy, fmaf(s.i[1], dx, s.i[0])) - b.base;
         const int i0 = (int)clampf(fi, 0.0f, maxi);
         scatter8(brick + i0, (size_t)sx, (size_t)sxy, s, v, [](T* q, float a) { atomicAdd(q, (T)a); });
@@ -474,8 +498,8 @@ __device__ __forceinline__ void scatter_lds_merged(const March& mr, int m0, int 
     };
     for (int k = 0; k < cnt; ++k) {
         const float fm = (float)m;
-        const Cell s = cell_of(fmaf(fm, mr.st[0], mr.qs[0]), fmaf(fm, mr.st[1], mr.qs[1]),
-                               fmaf(fm, mr.st[2], mr.qs[2]), bd);
+        const Cell s = cell_of_padded(fmaf(fm, mr.st[0], mr.qs[0]), fmaf(fm, mr.st[1], mr.qs[1]),
+                               fmaf(fm, mr.st[2], mr.qs[2]));
         const float fi = fmaf(s.i[2], dxy, fmaf(s.i[1], dx, s.i[0])) - b.base;
         const int i0 = (int)clampf(fi, 0.0f, maxi);
         const float gx = 1.0f - s.f[0], gy = 1.0f - s.f[1], gz = 1.0f - s.f[2];
