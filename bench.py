@@ -198,6 +198,11 @@ def run_single(args, cfg, workload):
     out = base_record(args, value, ms_step, workload,
                       {"valid_samples_per_direction": valid, "nominal_samples_per_direction": nominal})
     out["roofline"], out["gather_equivalent_hbm_frac"] = roofline_of(valid, fwd_ms, adj_ms)
+    out["config"]["tilings"] = [
+        {d: {k: (round(v, 4) if isinstance(v, float) else v)
+             for k, v in plan.get_tiling(i, ci).as_dict().items()}
+         for i, d in ((0, "project"), (1, "backproject"))}
+        for ci in range(len(cams))]
     if cfg["name"] == "plenoptic_128":
         dom = "backproject" if adj_ms >= fwd_ms else "project"
         out["roofline"]["traffic"] = counter_traffic(plan, dom)

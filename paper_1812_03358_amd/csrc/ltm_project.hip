@@ -507,15 +507,14 @@ __device__ __forceinline__ void scatter_lds_merged(const March& mr, int m0, int 
         const float a00 = gy * z0, a10 = s.f[1] * z0, a01 = gy * z1, a11 = s.f[1] * z1;
         const float w[8] = {gx * a00, s.f[0] * a00, gx * a10, s.f[0] * a10,
                             gx * a01, s.f[0] * a01, gx * a11, s.f[0] * a11};
-        if (i0 != cur) {
-            if (cur >= 0) flush(cur);
-            cur = i0;
+        // flush the previous cell's sums when the cell changes, then restart
+        // (keep = 0) or continue (keep = 1) them without a divergent branch
+        const bool change = i0 != cur;
+        if (change && cur >= 0) flush(cur);
+        const float keep = change ? 0.0f : 1.0f;
+        cur = i0;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) a[j] = w[j];
-        } else {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) a[j] += w[j];
-        }
+        for (int j = 0; j < 8; ++j) a[j] = fmaf(keep, a[j], w[j]);
         ++m;
         m = m == m1 ? m0 : m;
     }
