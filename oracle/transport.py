@@ -169,9 +169,12 @@ def angular_cells(cam: dict):
 
 def slice_factors(g: dict, cam: dict, basis: int):
     """Per slice iz and unmasked cell k: (Bs [nu, nx], Bt [nv, ny]) and the
-    scale dz / (K V^d)."""
+    scale dz / (K V^d).  The grid pitch may be one size or (s, t, depth)
+    sizes (the rotated grids of posed cameras)."""
     _check_head_on(cam)
-    nx, ny, nz, dx = g["nx"], g["ny"], g["nz"], g["pitch"]
+    nx, ny, nz = g["nx"], g["ny"], g["nz"]
+    pitch = g["pitch"]
+    hx, hy, dx = (pitch, pitch, pitch) if np.isscalar(pitch) else pitch   # s, t, depth sizes
     nu, nv, dp = cam["det_nu"], cam["det_nv"], cam["pixel_pitch"]
     L = -cam["lens_center"][2]
     D, F = cam["d_det"], cam["f_main"]
@@ -179,8 +182,8 @@ def slice_factors(g: dict, cam: dict, basis: int):
     K = cam["rays_u"] * cam["rays_v"]
     si = (np.arange(nu) + 0.5 - 0.5 * nu) * dp
     ti = (np.arange(nv) + 0.5 - 0.5 * nv) * dp
-    sj = (np.arange(nx) + 0.5 - 0.5 * nx) * dx
-    tj = (np.arange(ny) + 0.5 - 0.5 * ny) * dx
+    sj = (np.arange(nx) + 0.5 - 0.5 * nx) * hx
+    tj = (np.arange(ny) + 0.5 - 0.5 * ny) * hy
     X0p = T(D)
     Vd = detector_volume(basis, X0p, dp, d0s) * detector_volume(basis, X0p, dp, d0t)
     scale = dx / (K * Vd)
@@ -190,8 +193,8 @@ def slice_factors(g: dict, cam: dict, basis: int):
         X0q, Xpq, _ = single_lens_maps(zq, D, F)
         per = []
         for sk, tk in cells:
-            Bs = transport_factor(basis, Xpq, X0q, sk, d0s, si, dp, sj, dx)
-            Bt = transport_factor(basis, Xpq, X0q, tk, d0t, ti, dp, tj, dx)
+            Bs = transport_factor(basis, Xpq, X0q, sk, d0s, si, dp, sj, hx)
+            Bt = transport_factor(basis, Xpq, X0q, tk, d0t, ti, dp, tj, hy)
             per.append((Bs, Bt))
         out.append(per)
     return out, scale
@@ -217,3 +220,129 @@ def backproject(g: dict, cam: dict, y, basis: int = PILLBOX) -> np.ndarray:
         for Bs, Bt in per:
             x[iz] += Bt.T @ y @ Bs
     return (scale * x).reshape(-1)
+
+
+# --------------------------------------------------------------------------
+# rotated perspectives: scaling and shears with L2-projected resampling
+# --------------------------------------------------------------------------
+def _hat_antiderivative(d):
+    """Integral from -inf to d of max(0, 1 - |t|)."""
+    d = np.asarray(d, dtype=np.float64)
+    out = np.where(d <= -1.0, 0.0, 0.0)
+    m = (d > -1.0) & (d <= 0.0)
+    out = np.where(m, 0.5 * (d + 1.0) ** 2, out)
+    m = (d > 0.0) & (d < 1.0)
+    out = np.where(m, 1.0 - 0.5 * (1.0 - d) ** 2, out)
+    return np.where(d >= 1.0, 1.0, out)
+
+
+def shear_factor(zi, zj, h, shift, width):
+    """[E]_{ij} for one column of a shear: the L2 projection onto boxes of
+    size h (centres zi) of boxes of size h (centres zj) displaced by
+    shift + t, t uniform over [-width/2, width/2] across the column's other
+    coordinate: the mean over t of the box overlap h * hat(.) / h, a
+    piecewise quadratic in (zi - zj + shift)."""
+    d = (np.asarray(zi, np.float64)[:, None] - np.asarray(zj, np.float64)[None, :] + shift) / h
+    if width == 0.0:
+        return np.maximum(0.0, 1.0 - np.abs(d))
+    w = width / h
+    return (_hat_antiderivative(d + 0.5 * w) - _hat_antiderivative(d - 0.5 * w)) / w
+
+
+def azimuth_shears(phi_deg: float):
+    """Theta = D S_z S_x for a rotation about y by phi (|phi| <= 45 deg), in
+    the x-z plane: D = diag(cos, 1/cos), S_z: z += a x with a = -sin cos,
+    S_x: x += b z with b = tan.  Returns (cos, a, b)."""
+    if abs(phi_deg) > 45.0 + 1e-9:
+        raise ValueError("the three-shear rotation is used for |phi| <= 45 deg")
+    p = math.radians(phi_deg)
+    c, s = math.cos(p), math.sin(p)
+    return c, -s * c, s / c
+
+
+def rotated_grid(g: dict, phi_deg: float):
+    """Voxel sizes and counts of the rotated coefficients (camera-aligned s,
+    t, z'): sizes (d/cos, d, d cos); the shears widen the z' and s ranges so
+    that the sheared support fits."""
+    c, a, b = azimuth_shears(phi_deg)
+    d = g["pitch"]
+    hx, hz = d / c, d * c
+    nx, ny, nz = g["nx"], g["ny"], g["nz"]
+    nz2 = nz + 2 * int(math.ceil(0.5 * abs(a) * nx * hx / hz)) + 2
+    nx3 = nx + 2 * int(math.ceil(0.5 * abs(b) * nz2 * hz / hx)) + 2
+    return dict(hx=hx, hy=d, hz=hz, nx=nx3, ny=ny, nz=nz2, nx1=nx, nz1=nz, a=a, b=b, c=c)
+
+
+def _centres(n, h):
+    return (np.arange(n) + 0.5 - 0.5 * n) * h
+
+
+def rotate_azimuth(g: dict, x, phi_deg: float):
+    """x^r = E^x E^z x on the rotated grid (D only rescales the voxels):
+    x is (nz, ny, nx) natural, the result (nz2, ny, nx3) in camera axes."""
+    R = rotated_grid(g, phi_deg)
+    x = np.asarray(x, np.float64).reshape(g["nz"], g["ny"], g["nx"])
+    hx, hz, a, b = R["hx"], R["hz"], R["a"], R["b"]
+    z1, z2 = _centres(R["nz1"], hz), _centres(R["nz"], hz)
+    x1, x3 = _centres(R["nx1"], hx), _centres(R["nx"], hx)
+    # E^z: per x column, shift a * x_c, spread |a| hx
+    r = np.zeros((R["nz"], g["ny"], R["nx1"]))
+    for ix, xc in enumerate(x1):
+        E = shear_factor(z2, z1, hz, a * xc, abs(a) * hx)          # (nz2, nz1)
+        r[:, :, ix] = E @ x[:, :, ix]
+    # E^x: per z row, shift b * z_c, spread |b| hz
+    out = np.zeros((R["nz"], g["ny"], R["nx"]))
+    for iz, zc in enumerate(z2):
+        E = shear_factor(x3, x1, hx, b * zc, abs(b) * hz)           # (nx3, nx1)
+        out[iz] = r[iz] @ E.T
+    return out, R
+
+
+def rotate_azimuth_adjoint(g: dict, xr, phi_deg: float):
+    """(E^x E^z)^T applied to rotated coefficients."""
+    R = rotated_grid(g, phi_deg)
+    xr = np.asarray(xr, np.float64).reshape(R["nz"], g["ny"], R["nx"])
+    hx, hz, a, b = R["hx"], R["hz"], R["a"], R["b"]
+    z1, z2 = _centres(R["nz1"], hz), _centres(R["nz"], hz)
+    x1, x3 = _centres(R["nx1"], hx), _centres(R["nx"], hx)
+    r = np.zeros((R["nz"], g["ny"], R["nx1"]))
+    for iz, zc in enumerate(z2):
+        E = shear_factor(x3, x1, hx, b * zc, abs(b) * hz)
+        r[iz] = xr[iz] @ E
+    out = np.zeros((g["nz"], g["ny"], g["nx"]))
+    for ix, xc in enumerate(x1):
+        E = shear_factor(z2, z1, hz, a * xc, abs(a) * hx)
+        out[:, :, ix] = E.T @ r[:, :, ix]
+    return out
+
+
+def _camera_distance(cam: dict) -> float:
+    L = np.asarray(cam["lens_center"], np.float64)
+    ez = np.asarray(cam["axes"][6:9], np.float64)
+    if abs(np.linalg.norm(L + np.dot(-L, ez) * ez)) > 1e-9 * np.linalg.norm(L):
+        raise ValueError("the lens must lie on the camera axis through the grid centre")
+    if abs(cam["axes"][4] - 1.0) > 1e-12:
+        raise ValueError("only rotations about the grid's y axis (azimuth poses)")
+    return float(-np.dot(L, ez))
+
+
+def project_posed(g: dict, cam: dict, x, basis: int = PILLBOX) -> np.ndarray:
+    """A x for a single-lens camera at azimuth phi: rotate the coefficients
+    into the camera's axes (scaling and two shears), then the head-on
+    transport on the rotated grid's anisotropic voxels."""
+    phi = cam["phi_deg"]
+    xr, R = rotate_azimuth(g, x, phi)
+    head = dict(cam, axes=[1.0, 0, 0, 0, 1.0, 0, 0, 0, 1.0],
+                lens_center=[0.0, 0.0, -_camera_distance(cam)])
+    gr = dict(nx=R["nx"], ny=R["ny"], nz=R["nz"], pitch=(R["hx"], R["hy"], R["hz"]))
+    return project(gr, head, xr, basis)
+
+
+def backproject_posed(g: dict, cam: dict, y, basis: int = PILLBOX) -> np.ndarray:
+    phi = cam["phi_deg"]
+    R = rotated_grid(g, phi)
+    head = dict(cam, axes=[1.0, 0, 0, 0, 1.0, 0, 0, 0, 1.0],
+                lens_center=[0.0, 0.0, -_camera_distance(cam)])
+    gr = dict(nx=R["nx"], ny=R["ny"], nz=R["nz"], pitch=(R["hx"], R["hy"], R["hz"]))
+    xr = backproject(gr, head, y, basis)
+    return rotate_azimuth_adjoint(g, xr, phi).reshape(-1)

@@ -135,3 +135,135 @@ def test_agrees_with_ray_driven_oracle(orc, basis):
     y0 = orc.project(g, [cam], x.astype(np.float64).reshape(-1))
     assert abs(y1.sum() / y0.sum() - 1.0) < 1e-4
     assert np.linalg.norm(y1 - y0) / np.linalg.norm(y0) < 0.08
+
+
+# ---------------------------------------------------------------- rotations
+def test_shear_entries_equal_projection_integrals():
+    # [E]_ij = (1/(h_b h)) * integral over the target voxel (width h_b across,
+    # h along the sheared axis) of the source box displaced by a * u
+    rng = np.random.default_rng(4)
+    for _ in range(6):
+        h, hb = rng.uniform(0.5, 1.5), rng.uniform(0.5, 1.5)
+        a = rng.uniform(-0.9, 0.9)
+        c = rng.uniform(-3, 3)                       # the column's coordinate across
+        zi = np.array([rng.uniform(-2, 2)])
+        zj = np.array([rng.uniform(-2, 2)])
+        E = X.shear_factor(zi, zj, h, a * c, abs(a) * hb)[0, 0]
+        n = 1500
+        u = c - 0.5 * hb + (np.arange(n) + 0.5) * hb / n
+        z = zi[0] - 0.5 * h + (np.arange(n) + 0.5) * h / n
+        U, Z = np.meshgrid(u, z, indexing="ij")
+        inside = np.abs(Z + a * U - zj[0]) <= 0.5 * h      # the displaced source box
+        ref = inside.mean()
+        assert abs(E - ref) < 2e-3, (E, ref)
+
+
+def test_shear_conserves_mass_and_zero_shear_is_identity():
+    zj = (np.arange(20) - 9.5) * 0.8
+    zi = (np.arange(40) - 19.5) * 0.8
+    E = X.shear_factor(zi, zj, 0.8, 1.3, 0.6)
+    assert np.max(np.abs(E.sum(axis=0) - 1.0)) < 1e-12
+    I = X.shear_factor(zj, zj, 0.8, 0.0, 0.0)
+    assert np.max(np.abs(I - np.eye(20))) < 1e-15
+
+
+def test_azimuth_decomposition_reproduces_the_rotation():
+    for phi in (-45.0, -20.0, 0.0, 33.0):
+        c, a, b = X.azimuth_shears(phi)
+        D = np.diag([c, 1.0 / c])
+        Sz = np.array([[1.0, 0.0], [a, 1.0]])
+        Sx = np.array([[1.0, b], [0.0, 1.0]])
+        p = np.radians(phi)
+        theta = np.array([[np.cos(p), np.sin(p)], [-np.sin(p), np.cos(p)]])   # (s, z') -> (x, z)
+        assert np.allclose(D @ Sz @ Sx, theta, atol=1e-14)
+        ax = W.azimuth_axes(phi)
+        assert np.allclose(theta, [[ax[0], ax[6]], [ax[2], ax[8]]], atol=1e-14)
+    with pytest.raises(ValueError):
+        X.azimuth_shears(50.0)
+
+
+def test_rotated_blob_matches_the_rotated_function():
+    # a smooth Gaussian volume, rotated by the shears, against the Gaussian
+    # evaluated at the rotated grid's voxel centres mapped back to the world
+    n, d, sig = 24, 1.0, 3.0
+    g = W.grid(n, d)
+    q = (np.arange(n) + 0.5 - 0.5 * n) * d
+    cen = np.array([1.5, -0.7, 2.2])                 # x, y, z
+    Z, Y, Xg = np.meshgrid(q, q, q, indexing="ij")
+    vol = np.exp(-((Xg - cen[0]) ** 2 + (Y - cen[1]) ** 2 + (Z - cen[2]) ** 2) / (2 * sig ** 2))
+    for phi in (25.0, -40.0):
+        xr, R = X.rotate_azimuth(g, vol, phi)
+        s = (np.arange(R["nx"]) + 0.5 - 0.5 * R["nx"]) * R["hx"]
+        t = (np.arange(R["ny"]) + 0.5 - 0.5 * R["ny"]) * R["hy"]
+        zp = (np.arange(R["nz"]) + 0.5 - 0.5 * R["nz"]) * R["hz"]
+        ax = np.array(W.azimuth_axes(phi)).reshape(3, 3)
+        ZP, T, S = np.meshgrid(zp, t, s, indexing="ij")
+        P = S[..., None] * ax[0] + T[..., None] * ax[1] + ZP[..., None] * ax[2]
+        ref = np.exp(-((P[..., 0] - cen[0]) ** 2 + (P[..., 1] - cen[1]) ** 2 +
+                       (P[..., 2] - cen[2]) ** 2) / (2 * sig ** 2))
+        err = np.linalg.norm(xr - ref) / np.linalg.norm(ref)
+        assert err < 0.03, (phi, err)
+        # the shears conserve the integral (voxel volume d^3 before and after)
+        assert abs(xr.sum() * R["hx"] * R["hy"] * R["hz"] / (vol.sum() * d ** 3) - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("phi", [20.0, -35.0])
+def test_posed_transport_agrees_with_ray_driven_oracle(orc, phi):
+    g = W.grid(24, 1.0)
+    cam = W.single_lens_camera(256, (4, 4), 96, phi_deg=phi)
+    x = W.blobs(24, seed=3, count=4)
+    y1 = X.project_posed(g, cam, x, X.PILLBOX)
+    y0 = orc.project(g, [cam], x.astype(np.float64).reshape(-1))
+    assert abs(y1.sum() / y0.sum() - 1.0) < 1e-3
+    assert np.linalg.norm(y1 - y0) / np.linalg.norm(y0) < 0.08
+
+
+def test_posed_backprojection_is_the_transpose():
+    g = W.grid((5, 4, 6), 1.0)
+    cam = W.single_lens_camera(12, (2, 2), 4, phi_deg=30.0, distance=300.0)
+    N, M = 120, 144
+    A = np.zeros((M, N))
+    for j in range(N):
+        e = np.zeros(N)
+        e[j] = 1.0
+        A[:, j] = X.project_posed(g, cam, e, X.DIRAC)
+    assert np.count_nonzero(A) > 0.02 * A.size
+    y = np.random.default_rng(6).uniform(-1, 1, M)
+    ref = A.T @ y
+    assert np.max(np.abs(X.backproject_posed(g, cam, y, X.DIRAC) - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_rotation_stages_equal_numerical_projections():
+    # one row of voxels of a 6 x 1 x 6 grid (random values), rotated by
+    # 30 deg: each shear stage against the projection integral of its
+    # displaced boxes, evaluated on a point lattice (independent of the
+    # closed-form piecewise quadratic)
+    n, d, phi = 6, 1.0, 30.0
+    g = W.grid((n, 1, n), d)
+    vol = np.zeros((n, 1, n))
+    vol[2, 0, :] = np.random.default_rng(8).uniform(0.5, 1.5, n)
+    xr, R = X.rotate_azimuth(g, vol, phi)
+    hx, hz, a, b = R["hx"], R["hz"], R["a"], R["b"]
+    x1 = (np.arange(R["nx1"]) + 0.5 - 0.5 * R["nx1"]) * hx
+    z1 = (np.arange(R["nz1"]) + 0.5 - 0.5 * R["nz1"]) * hz
+    z2 = (np.arange(R["nz"]) + 0.5 - 0.5 * R["nz"]) * hz
+    x3 = (np.arange(R["nx"]) + 0.5 - 0.5 * R["nx"]) * hx
+    m = 400
+    fr = (np.arange(m) + 0.5) / m - 0.5
+    # stage 1: r[iz2, ix1] = v(ix1) * mean over the target cell of [z + a x in the source z-cell]
+    r = np.zeros((R["nz"], R["nx1"]))
+    for ix in range(R["nx1"]):
+        U = x1[ix] + fr * hx
+        for iz in range(R["nz"]):
+            zz, uu = np.meshgrid(z2[iz] + fr * hz, U, indexing="ij")
+            r[iz, ix] = vol[2, 0, ix] * np.mean(np.abs(zz + a * uu - z1[2]) <= 0.5 * hz)
+    # stage 2: out[iz, j] = sum_ix1 r[iz, ix1] * mean over the cell of [x + b z in ix1]
+    out = np.zeros((R["nz"], R["nx"]))
+    for iz in range(R["nz"]):
+        for j in range(R["nx"]):
+            xx, zz = np.meshgrid(x3[j] + fr * hx, z2[iz] + fr * hz, indexing="ij")
+            sx = xx + b * zz
+            for ix in range(R["nx1"]):
+                out[iz, j] += r[iz, ix] * np.mean(np.abs(sx - x1[ix]) <= 0.5 * hx)
+    assert np.max(np.abs(xr[:, 0, :] - out)) < 5e-3 * xr.max()
+    assert xr.max() > 0.1
