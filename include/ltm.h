@@ -369,12 +369,19 @@ ltm_status ltm_nn_add(float* a, const float* b, uint64_t n, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* The paper's own discretization (light-field discretization, light
- * transport, object-model and camera-model sections; Dirac and pillbox
- * transport tables), for a single-lens camera looking head-on along +z at the
- * grid (axes = identity, lens_center = (0, 0, -distance), every slice in front
- * of the lens).  The volume is collapsed into its nz slices; slice iz at
- * camera depth z = distance + (iz + 1/2 - nz/2) pitch radiates the light
- * field dz * x[iz] for every angular cell.  The angular plane is the main
+ * transport, object-model, camera-model and rotated-perspective sections;
+ * Dirac and pillbox transport tables), for a single-lens camera at azimuth
+ * phi about the grid's y axis (e_t = +y), |phi| <= 45 deg, with the lens on
+ * the camera axis through the grid centre.  A posed camera first rotates the
+ * volume into its axes as the paper does: with c = cos phi the voxels scale
+ * to (pitch/c, pitch, pitch c) along (s, t, depth), then a z shear
+ * (z += -sin(phi) c x) and an x shear (x += tan(phi) z) resample the
+ * coefficients, each the L2 projection of the sheared boxes (a piecewise
+ * quadratic kernel); the rotated grid grows to nz' = nz + 2 ceil(|sin c| nx
+ * / (2 c^2)) + 2 slices and nx' = nx + 2 ceil(|tan| nz' c^2 / 2) + 2 columns.
+ * The (rotated) volume is collapsed into its slices; slice iz at camera
+ * depth z = distance + (iz + 1/2 - nz'/2) dz radiates the light field
+ * dz * x[iz] for every angular cell.  The angular plane is the main
  * lens, divided into rays_u x rays_v cells (each 1..64) of size
  * 2 r_main / rays_* over its bounding square; cells whose centre lies
  * outside the lens disc are masked.  Each cell's transport is the Kronecker product of an s and a

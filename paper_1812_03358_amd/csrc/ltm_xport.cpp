@@ -29,8 +29,14 @@ struct ltm_xport {
         std::vector<int32_t> start;   // pairs * rows
         std::vector<float> w;         // pairs * width * rows (weight-major)
     } bt, cs, cst, btt;
+    // posed cameras: rotation of the natural grid into the camera's axes
+    bool rot = false;
+    int nxr = 0, nyr = 0, nzr = 0;          // transport grid (rotated, or the natural one)
+    Band ez, ezt, ex, ext;
     uint64_t off_bt_s = 0, off_bt_w = 0, off_cs_s = 0, off_cs_w = 0, off_cst_s = 0, off_cst_w = 0,
              off_btt_s = 0, off_btt_w = 0, off_mid = 0, ws_bytes = 0;
+    uint64_t off_ez_s = 0, off_ez_w = 0, off_ezt_s = 0, off_ezt_w = 0, off_ex_s = 0, off_ex_w = 0,
+             off_ext_s = 0, off_ext_w = 0, off_r1 = 0, off_xr = 0;
     char* ws = nullptr;
     bool bound = false;
 };
@@ -156,6 +162,41 @@ void transpose(const ltm_xport::Band& a, int pairs, int cols, ltm_xport::Band& t
 
 uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
 
+// Rotated perspectives: the L2 projection of boxes of size h displaced by
+// shift + t, t uniform over [-width/2, width/2] (the shear across the
+// column's other coordinate), onto boxes of size h: the mean of the box
+// overlap fraction hat(d) = max(0, 1 - |d|) over the window, a piecewise
+// quadratic in d = (zi - zj + shift) / h.
+double hat_integral(double d)
+{
+    if (d <= -1.0) return 0.0;
+    if (d <= 0.0) return 0.5 * (d + 1.0) * (d + 1.0);
+    if (d < 1.0) return 1.0 - 0.5 * (1.0 - d) * (1.0 - d);
+    return 1.0;
+}
+
+double shear_entry(double zi, double zj, double h, double shift, double width)
+{
+    const double d = (zi - zj + shift) / h;
+    if (width == 0.0) return std::max(0.0, 1.0 - std::fabs(d));
+    const double w = width / h;
+    return (hat_integral(d + 0.5 * w) - hat_integral(d - 0.5 * w)) / w;
+}
+
+// One column of a shear: rows = output centres zi, columns = input centres zj.
+Rows shear_rows(int n_out, int n_in, double h, double shift, double width)
+{
+    Rows rows(n_out);
+    for (int i = 0; i < n_out; ++i) {
+        const double zi = (i + 0.5 - 0.5 * n_out) * h;
+        for (int j = 0; j < n_in; ++j) {
+            const double v = shear_entry(zi, (j + 0.5 - 0.5 * n_in) * h, h, shift, width);
+            if (v != 0.0) rows[i].emplace_back(j, v);
+        }
+    }
+    return rows;
+}
+
 }  // namespace
 }  // namespace ltm
 
@@ -177,40 +218,64 @@ ltm_status ltm_xport_create(const ltm_grid* g, const ltm_camera* c, uint32_t bas
     if (st != LTM_OK) return st;
     if (c->kind != LTM_SINGLE_LENS)
         return fail(LTM_ERR_UNSUPPORTED, "the transport operator models single-lens cameras");
-    for (int a = 0; a < 9; ++a)
-        if (std::fabs(c->axes[a] - ((a % 4) == 0 ? 1.0 : 0.0)) > 1e-12)
-            return fail(LTM_ERR_UNSUPPORTED, "the transport operator needs a head-on camera (axes = identity)");
-    const double L = -c->lens_center_mm[2];
-    if (std::fabs(c->lens_center_mm[0]) > 1e-12 * L || std::fabs(c->lens_center_mm[1]) > 1e-12 * L)
-        return fail(LTM_ERR_UNSUPPORTED, "the transport operator needs the lens on the z axis");
-    if (!(L - 0.5 * g->nz * g->pitch_mm > 0.0))
+    // pose: azimuth phi about the grid's y axis, |phi| <= 45 deg, the lens on
+    // the camera axis through the grid centre
+    const double* es = c->axes;
+    const double* et = c->axes + 3;
+    const double* ez = c->axes + 6;
+    if (std::fabs(et[1] - 1.0) > 1e-12 || std::fabs(es[1]) > 1e-12 || std::fabs(ez[1]) > 1e-12)
+        return fail(LTM_ERR_UNSUPPORTED, "the transport operator needs an azimuth pose (e_t = +y)");
+    const double phi = std::atan2(ez[0], ez[2]);
+    if (std::fabs(phi) > 0.25 * M_PI + 1e-12)
+        return fail(LTM_ERR_UNSUPPORTED, "the transport operator's shear rotation needs |phi| <= 45 deg");
+    const double L = -(c->lens_center_mm[0] * ez[0] + c->lens_center_mm[1] * ez[1] +
+                       c->lens_center_mm[2] * ez[2]);
+    for (int a = 0; a < 3; ++a)
+        if (std::fabs(c->lens_center_mm[a] + L * ez[a]) > 1e-9 * std::fabs(L))
+            return fail(LTM_ERR_UNSUPPORTED, "the transport operator needs the lens on the camera axis through the grid centre");
+    const double cphi = std::cos(phi), sphi = std::sin(phi);
+    const bool rot = std::fabs(sphi) > 1e-15;
+    const double sa = -sphi * cphi, sb = sphi / cphi;           // S_z: z += sa x, S_x: x += sb z
+    const double d = g->pitch_mm;
+    const double hx = rot ? d / cphi : d, hy = d, hz = rot ? d * cphi : d;
+    int nzr = (int)g->nz, nxr = (int)g->nx;
+    if (rot) {
+        nzr = (int)g->nz + 2 * (int)std::ceil(0.5 * std::fabs(sa) * g->nx * hx / hz) + 2;
+        nxr = (int)g->nx + 2 * (int)std::ceil(0.5 * std::fabs(sb) * nzr * hz / hx) + 2;
+    }
+    if (!(L - 0.5 * nzr * hz > 0.0))
         return fail(LTM_ERR_INVALID, "every slice must lie in front of the lens");
-    const uint64_t mid = (uint64_t)g->nz * c->rays_v * c->det_nv * (uint64_t)g->nx;
+    const uint64_t mid = (uint64_t)nzr * c->rays_v * c->det_nv * (uint64_t)nxr;
     if (mid > (1ull << 34)) return fail(LTM_ERR_INVALID, "intermediate larger than 2^34 values");
     ltm_xport* t = new ltm_xport();
     t->grid = *g;
     t->cam = *c;
     t->basis = basis;
     t->kt = (int)c->rays_v;
+    t->rot = rot;
+    t->nxr = nxr;
+    t->nyr = (int)g->ny;
+    t->nzr = nzr;
 
-    const int nx = (int)g->nx, ny = (int)g->ny, nz = (int)g->nz;
+    // transport on the (rotated) grid: voxel sizes hx (s), hy (t), hz (depth)
+    const int nx = nxr, ny = (int)g->ny, nz = nzr;
     const int nu = (int)c->det_nu, nv = (int)c->det_nv, Ks = (int)c->rays_u, Kt = (int)c->rays_v;
-    const double dx = g->pitch_mm, dp = c->pixel_pitch_mm, D = c->d_det_mm, F = c->f_main_mm;
+    const double dp = c->pixel_pitch_mm, D = c->d_det_mm, F = c->f_main_mm;
     const double r = c->r_main_mm, d0s = 2.0 * r / Ks, d0t = 2.0 * r / Kt;
     const double Vd = axis_volume((int)basis, D, dp, d0s) * axis_volume((int)basis, D, dp, d0t);
-    const double scale = dx / ((double)Ks * Kt * Vd);
+    const double scale = hz / ((double)Ks * Kt * Vd);
     std::vector<Rows> bt_pairs, cs_pairs;
     bt_pairs.reserve((size_t)nz * Kt);
     cs_pairs.reserve((size_t)nz * Kt);
     std::vector<std::pair<int, double>> tmp;
     for (int iz = 0; iz < nz; ++iz) {
-        const double z = L + (iz + 0.5 - 0.5 * nz) * dx;
+        const double z = L + (iz + 0.5 - 0.5 * nz) * hz;
         for (int kt = 0; kt < Kt; ++kt) {
             const double tk = (kt + 0.5) * d0t - r;
             // t factor (shared by the row's cells; unit scale)
             Rows bt(nv);
             const Kernel1D kt1 = kernel_of((int)basis, z, D, F, tk, d0t, dp);
-            for (int v = 0; v < nv; ++v) factor_row(kt1, (v + 0.5 - 0.5 * nv) * dp, dx, ny, 1.0, bt[v]);
+            for (int v = 0; v < nv; ++v) factor_row(kt1, (v + 0.5 - 0.5 * nv) * dp, hy, ny, 1.0, bt[v]);
             // s factors of the row's unmasked cells, summed, with the scale
             std::vector<std::vector<double>> dense(nu);
             std::vector<int> lo(nu, nx), hi(nu, -1);
@@ -220,7 +285,7 @@ ltm_status ltm_xport_create(const ltm_grid* g, const ltm_camera* c, uint32_t bas
                 const Kernel1D k1 = kernel_of((int)basis, z, D, F, sk, d0s, dp);
                 for (int u = 0; u < nu; ++u) {
                     tmp.clear();
-                    factor_row(k1, (u + 0.5 - 0.5 * nu) * dp, dx, nx, scale, tmp);
+                    factor_row(k1, (u + 0.5 - 0.5 * nu) * dp, hx, nx, scale, tmp);
                     if (dense[u].empty() && !tmp.empty()) dense[u].assign(nx, 0.0);
                     for (const auto& kv : tmp) {
                         dense[u][kv.first] += kv.second;
@@ -242,6 +307,20 @@ ltm_status ltm_xport_create(const ltm_grid* g, const ltm_camera* c, uint32_t bas
     const int pairs = nz * Kt;
     transpose(t->cs, pairs, nx, t->cst);
     transpose(t->bt, pairs, ny, t->btt);
+    if (rot) {
+        // E^z per natural x column (shift sa * x, spread |sa| hx), then E^x
+        // per sheared z row (shift sb * z, spread |sb| hz)
+        const int nx1 = (int)g->nx, nz1 = (int)g->nz;
+        std::vector<Rows> ezp, exp_;
+        for (int x1 = 0; x1 < nx1; ++x1)
+            ezp.push_back(shear_rows(nzr, nz1, hz, sa * (x1 + 0.5 - 0.5 * nx1) * hx, std::fabs(sa) * hx));
+        for (int z = 0; z < nzr; ++z)
+            exp_.push_back(shear_rows(nxr, nx1, hx, sb * (z + 0.5 - 0.5 * nzr) * hz, std::fabs(sb) * hz));
+        pack(ezp, nzr, t->ez);
+        pack(exp_, nxr, t->ex);
+        transpose(t->ez, nx1, nz1, t->ezt);
+        transpose(t->ex, nzr, nx1, t->ext);
+    }
     uint64_t off = 0;
     auto place = [&](uint64_t& o, uint64_t bytes) { o = off; off = align256(off + bytes); };
     place(t->off_bt_s, t->bt.start.size() * 4);
@@ -253,6 +332,18 @@ ltm_status ltm_xport_create(const ltm_grid* g, const ltm_camera* c, uint32_t bas
     place(t->off_btt_s, t->btt.start.size() * 4);
     place(t->off_btt_w, t->btt.w.size() * 4);
     place(t->off_mid, mid * 4);
+    if (rot) {
+        place(t->off_ez_s, t->ez.start.size() * 4);
+        place(t->off_ez_w, t->ez.w.size() * 4);
+        place(t->off_ezt_s, t->ezt.start.size() * 4);
+        place(t->off_ezt_w, t->ezt.w.size() * 4);
+        place(t->off_ex_s, t->ex.start.size() * 4);
+        place(t->off_ex_w, t->ex.w.size() * 4);
+        place(t->off_ext_s, t->ext.start.size() * 4);
+        place(t->off_ext_w, t->ext.w.size() * 4);
+        place(t->off_r1, (uint64_t)nzr * g->ny * g->nx * 4);
+        place(t->off_xr, (uint64_t)nzr * g->ny * nxr * 4);
+    }
     t->ws_bytes = off;
     *out = t;
     clear_error();
@@ -293,8 +384,17 @@ ltm_status ltm_xport_bind_workspace(ltm_xport* t, void* ws, uint64_t bytes, void
         {t->off_cst_s, t->cst.start.data(), t->cst.start.size() * 4},
         {t->off_cst_w, t->cst.w.data(), t->cst.w.size() * 4},
         {t->off_btt_s, t->btt.start.data(), t->btt.start.size() * 4},
-        {t->off_btt_w, t->btt.w.data(), t->btt.w.size() * 4}};
+        {t->off_btt_w, t->btt.w.data(), t->btt.w.size() * 4},
+        {t->off_ez_s, t->ez.start.data(), t->ez.start.size() * 4},
+        {t->off_ez_w, t->ez.w.data(), t->ez.w.size() * 4},
+        {t->off_ezt_s, t->ezt.start.data(), t->ezt.start.size() * 4},
+        {t->off_ezt_w, t->ezt.w.data(), t->ezt.w.size() * 4},
+        {t->off_ex_s, t->ex.start.data(), t->ex.start.size() * 4},
+        {t->off_ex_w, t->ex.w.data(), t->ex.w.size() * 4},
+        {t->off_ext_s, t->ext.start.data(), t->ext.start.size() * 4},
+        {t->off_ext_w, t->ext.w.data(), t->ext.w.size() * 4}};
     for (const Up& u : ups) {
+        if (u.n == 0) continue;
         hipError_t e = hipMemcpyAsync(base + u.off, u.src, u.n, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "upload transport tables");
     }
@@ -312,9 +412,9 @@ namespace {
 ltm::XportDev dev_of(const ltm_xport* t)
 {
     ltm::XportDev d{};
-    d.nx = (int)t->grid.nx;
-    d.ny = (int)t->grid.ny;
-    d.nz = (int)t->grid.nz;
+    d.nx = t->nxr;
+    d.ny = t->nyr;
+    d.nz = t->nzr;
     d.nu = (int)t->cam.det_nu;
     d.nv = (int)t->cam.det_nv;
     d.kt = t->kt;
@@ -334,6 +434,31 @@ ltm::XportDev dev_of(const ltm_xport* t)
     return d;
 }
 
+ltm::ShearDev shear_of(const ltm_xport* t)
+{
+    ltm::ShearDev r{};
+    r.nx1 = (int)t->grid.nx;
+    r.nz1 = (int)t->grid.nz;
+    r.nx = t->nxr;
+    r.ny = t->nyr;
+    r.nz = t->nzr;
+    auto band = [&](const ltm_xport::Band& b, uint64_t so, uint64_t wo) {
+        ltm::BandDev q;
+        q.start = reinterpret_cast<const int32_t*>(t->ws + so);
+        q.w = reinterpret_cast<const float*>(t->ws + wo);
+        q.rows = b.rows;
+        q.width = b.width;
+        return q;
+    };
+    r.ez = band(t->ez, t->off_ez_s, t->off_ez_w);
+    r.ezt = band(t->ezt, t->off_ezt_s, t->off_ezt_w);
+    r.ex = band(t->ex, t->off_ex_s, t->off_ex_w);
+    r.ext = band(t->ext, t->off_ext_s, t->off_ext_w);
+    r.r1 = reinterpret_cast<float*>(t->ws + t->off_r1);
+    r.xr = reinterpret_cast<float*>(t->ws + t->off_xr);
+    return r;
+}
+
 }  // namespace
 
 extern "C" {
@@ -342,7 +467,15 @@ ltm_status ltm_xport_project(ltm_xport* t, const float* x, float* y, void* strea
 {
     if (!t || !x || !y) return fail(LTM_ERR_INVALID, "null argument");
     if (!t->bound) return fail(LTM_ERR_WORKSPACE, "transport operator has no bound workspace");
-    hipError_t e = launch_xport_project(dev_of(t), x, y, static_cast<hipStream_t>(stream));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    if (t->rot) {
+        const ltm::ShearDev r = shear_of(t);
+        e = launch_shear_forward(r, x, s);
+        if (e == hipSuccess) e = launch_xport_project(dev_of(t), r.xr, y, s);
+    } else {
+        e = launch_xport_project(dev_of(t), x, y, s);
+    }
     return e == hipSuccess ? LTM_OK : hip_fail(e, "transport project");
 }
 
@@ -350,7 +483,15 @@ ltm_status ltm_xport_backproject(ltm_xport* t, const float* y, float* x, void* s
 {
     if (!t || !x || !y) return fail(LTM_ERR_INVALID, "null argument");
     if (!t->bound) return fail(LTM_ERR_WORKSPACE, "transport operator has no bound workspace");
-    hipError_t e = launch_xport_backproject(dev_of(t), y, x, static_cast<hipStream_t>(stream));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    if (t->rot) {
+        const ltm::ShearDev r = shear_of(t);
+        e = launch_xport_backproject(dev_of(t), y, r.xr, s);
+        if (e == hipSuccess) e = launch_shear_adjoint(r, x, s);
+    } else {
+        e = launch_xport_backproject(dev_of(t), y, x, s);
+    }
     return e == hipSuccess ? LTM_OK : hip_fail(e, "transport backproject");
 }
 

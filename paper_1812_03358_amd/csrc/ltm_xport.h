@@ -27,7 +27,22 @@ struct XportDev {
     float* mid;    // nz * kt * nv * nx intermediate
 };
 
+// Rotation of the volume into a posed camera's axes (scaling plus two
+// shears, each an L2-projected 1-D resampling): natural grid (nz1, ny, nx1)
+// -> z-sheared (nz, ny, nx1) -> x-sheared (nz, ny, nx), the transport's grid.
+struct ShearDev {
+    int nx1, nz1, nx, ny, nz;
+    BandDev ez;    // per natural column x1: rows = sheared z,  columns = natural z
+    BandDev ezt;   // transpose:             rows = natural z,  columns = sheared z
+    BandDev ex;    // per sheared row z:     rows = rotated x,  columns = natural x
+    BandDev ext;   // transpose:             rows = natural x,  columns = rotated x
+    float* r1;     // z-sheared volume
+    float* xr;     // rotated volume
+};
+
 hipError_t launch_xport_project(const XportDev& d, const float* x, float* y, hipStream_t s);
 hipError_t launch_xport_backproject(const XportDev& d, const float* y, float* x, hipStream_t s);
+hipError_t launch_shear_forward(const ShearDev& r, const float* x, hipStream_t s);
+hipError_t launch_shear_adjoint(const ShearDev& r, float* x, hipStream_t s);
 
 }  // namespace ltm

@@ -224,6 +224,91 @@ __global__ __launch_bounds__(kBlock) void k_minor_adj(XportDev d, float* __restr
     }
 }
 
+// ---------------------------------------------------------------- shears
+// r1[z][y][x1] = sum_k ez.w[x1][k][z] * x[start + k][y][x1]
+__global__ __launch_bounds__(kBlock) void k_shear_z(ShearDev r, const float* __restrict__ x)
+{
+    const size_t total = (size_t)r.nz * r.ny * r.nx1;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * kBlock) {
+        const int x1 = (int)(i % r.nx1);
+        const size_t q = i / r.nx1;
+        const int y = (int)(q % r.ny);
+        const int z = (int)(q / r.ny);
+        const int st = r.ez.start[(size_t)x1 * r.nz + z];
+        const float* w = r.ez.w + (size_t)x1 * r.ez.width * r.nz + z;
+        double acc = 0.0;
+        for (int k = 0; k < r.ez.width; ++k) {
+            const int zs = st + k;
+            if (zs < r.nz1) acc += (double)(w[(size_t)k * r.nz] * x[((size_t)zs * r.ny + y) * r.nx1 + x1]);
+        }
+        r.r1[i] = (float)acc;
+    }
+}
+
+// xr[z][y][x] = sum_k ex.w[z][k][x] * r1[z][y][start + k]
+__global__ __launch_bounds__(kBlock) void k_shear_x(ShearDev r)
+{
+    const size_t total = (size_t)r.nz * r.ny * r.nx;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * kBlock) {
+        const int x = (int)(i % r.nx);
+        const size_t q = i / r.nx;
+        const int z = (int)(q / r.ny);
+        const int st = r.ex.start[(size_t)z * r.nx + x];
+        const float* w = r.ex.w + (size_t)z * r.ex.width * r.nx + x;
+        const float* row = r.r1 + q * r.nx1;
+        double acc = 0.0;
+        for (int k = 0; k < r.ex.width; ++k) {
+            const int xs = st + k;
+            if (xs < r.nx1) acc += (double)(w[(size_t)k * r.nx] * row[xs]);
+        }
+        r.xr[i] = (float)acc;
+    }
+}
+
+// r1[z][y][x1] = sum_k ext.w[z][k][x1] * xr[z][y][start + k]
+__global__ __launch_bounds__(kBlock) void k_shear_x_t(ShearDev r)
+{
+    const size_t total = (size_t)r.nz * r.ny * r.nx1;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * kBlock) {
+        const int x1 = (int)(i % r.nx1);
+        const size_t q = i / r.nx1;
+        const int z = (int)(q / r.ny);
+        const int st = r.ext.start[(size_t)z * r.nx1 + x1];
+        const float* w = r.ext.w + (size_t)z * r.ext.width * r.nx1 + x1;
+        const float* row = r.xr + q * r.nx;
+        double acc = 0.0;
+        for (int k = 0; k < r.ext.width; ++k) {
+            const int xs = st + k;
+            if (xs < r.nx) acc += (double)(w[(size_t)k * r.nx1] * row[xs]);
+        }
+        r.r1[i] = (float)acc;
+    }
+}
+
+// x[z1][y][x1] = sum_k ezt.w[x1][k][z1] * r1[start + k][y][x1]
+__global__ __launch_bounds__(kBlock) void k_shear_z_t(ShearDev r, float* __restrict__ x)
+{
+    const size_t total = (size_t)r.nz1 * r.ny * r.nx1;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * kBlock) {
+        const int x1 = (int)(i % r.nx1);
+        const size_t q = i / r.nx1;
+        const int y = (int)(q % r.ny);
+        const int z1 = (int)(q / r.ny);
+        const int st = r.ezt.start[(size_t)x1 * r.nz1 + z1];
+        const float* w = r.ezt.w + (size_t)x1 * r.ezt.width * r.nz1 + z1;
+        double acc = 0.0;
+        for (int k = 0; k < r.ezt.width; ++k) {
+            const int zs = st + k;
+            if (zs < r.nz) acc += (double)(w[(size_t)k * r.nz1] * r.r1[((size_t)zs * r.ny + y) * r.nx1 + x1]);
+        }
+        x[i] = (float)acc;
+    }
+}
+
 unsigned grid_for(size_t n)
 {
     const size_t b = (n + kBlock - 1) / kBlock;
@@ -247,6 +332,24 @@ hipError_t launch_xport_project(const XportDev& d, const float* x, float* y, hip
     case 4: hipLaunchKernelGGL(k_major_fwd_w<4>, g, b, 0, s, d, y); break;
     default: hipLaunchKernelGGL(k_major_fwd, g, b, 0, s, d, y); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_shear_forward(const ShearDev& r, const float* x, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_shear_z, dim3(grid_for((size_t)r.nz * r.ny * r.nx1)), dim3(kBlock), 0, s, r, x);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_shear_x, dim3(grid_for((size_t)r.nz * r.ny * r.nx)), dim3(kBlock), 0, s, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_shear_adjoint(const ShearDev& r, float* x, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_shear_x_t, dim3(grid_for((size_t)r.nz * r.ny * r.nx1)), dim3(kBlock), 0, s, r);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_shear_z_t, dim3(grid_for((size_t)r.nz1 * r.ny * r.nx1)), dim3(kBlock), 0, s, r, x);
     return hipGetLastError();
 }
 

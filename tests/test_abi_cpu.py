@@ -160,7 +160,12 @@ def test_transport_operator_validation(L):
         assert L.lib().ltm_xport_project(h, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == \
             L.LTM_ERR_WORKSPACE
         L.lib().ltm_xport_destroy(h)
-    cases = [(W.single_lens_camera(128, (4, 4), 8, phi_deg=20.0), L.LTM_ERR_UNSUPPORTED, "head-on"),
+    for phi in (20.0, -45.0):                            # posed: the shear rotation
+        cam = W.single_lens_camera(128, (4, 4), 8, phi_deg=phi)
+        assert L.lib().ltm_xport_create(ctypes.byref(L.make_grid(g)), L.make_cameras([cam]), 1,
+                                        ctypes.byref(h)) == 0
+        L.lib().ltm_xport_destroy(h)
+    cases = [(W.single_lens_camera(128, (4, 4), 8, phi_deg=50.0), L.LTM_ERR_UNSUPPORTED, "45 deg"),
              (W.plenoptic_camera(64, 4, (2, 2), 8), L.LTM_ERR_UNSUPPORTED, "single-lens"),
              (W.single_lens_camera(128, (4, 4), 8, distance=10.0), L.LTM_ERR_INVALID, "in front")]
     for cam, status, needle in cases:

@@ -100,3 +100,49 @@ def test_transport_paper_size_dot_and_ray_model(ltm, orc):
     assert dot < 1e-9
     assert abs(Ax.sum() / Ar.sum() - 1.0) < 1e-3
     assert d < 0.1
+
+
+@pytest.mark.parametrize("phi,basis", [(20.0, 1), (-35.0, 0), (45.0, 1)])
+def test_posed_transport_matches_oracle(ltm, phi, basis):
+    # the paper's rotated perspective: scaling and two L2-projected shears,
+    # then the transport on the rotated grid's anisotropic voxels
+    g = W.grid((18, 14, 16), 1.0)
+    cam = W.single_lens_camera(160, (4, 4), 8, phi_deg=phi)
+    x = W.flame(18, seed=6)[:16, :14, :18]
+    y = W.uniform_random(160 * 160, seed=7)
+    op = ltm.Transport(g, cam, basis)
+    Ax = op.project(_dev(x)).cpu().numpy()
+    Aty = op.backproject(_dev(y)).cpu().numpy()
+    ref_Ax = OT.project_posed(g, cam, x, basis)
+    ref_Aty = OT.backproject_posed(g, cam, y, basis)
+    x64, y64 = x.astype(np.float64).reshape(-1), y.astype(np.float64)
+    dot = abs(Ax.astype(np.float64) @ y64 - x64 @ Aty.astype(np.float64)) / (
+        np.linalg.norm(Ax) * np.linalg.norm(y64))
+    e1, e2 = rel_l2(Ax, ref_Ax), rel_l2(Aty, ref_Aty)
+    print(f"posed transport phi={phi} basis={basis}: A {e1:.2e} A^T {e2:.2e} dot {dot:.2e}", flush=True)
+    assert np.linalg.norm(ref_Ax) > 0
+    assert e1 < 1e-5 and e2 < 1e-5
+    assert dot < 1e-9
+
+
+def test_posed_transport_paper_size_vs_ray_model(ltm):
+    # single-lens 1024^2 at -30 deg (the three-camera experiment's side
+    # camera), 100^3 at 1 mm, 8x8 pillbox cells
+    g = W.grid(100, 1.0)
+    cam = W.single_lens_camera(1024, (8, 8), 200, phi_deg=-30.0)
+    x = W.flame(100, seed=5)
+    op = ltm.Transport(g, cam, 1)
+    Ax = op.project(_dev(x)).cpu().numpy()
+    y = W.uniform_random(1024 * 1024, seed=9)
+    Aty = op.backproject(_dev(y)).cpu().numpy()
+    x64, y64 = x.astype(np.float64).reshape(-1), y.astype(np.float64)
+    dot = abs(Ax.astype(np.float64) @ y64 - x64 @ Aty.astype(np.float64)) / (
+        np.linalg.norm(Ax) * np.linalg.norm(y64))
+    plan = ltm.Plan(g, [cam])
+    Ar = plan.project(_dev(x)).cpu().numpy()
+    d = rel_l2(Ax, Ar)
+    print(f"posed transport 1024^2 -30 deg: dot {dot:.2e}, vs ray-driven {d:.3f}, "
+          f"sums {Ax.sum() / Ar.sum():.5f}", flush=True)
+    assert dot < 1e-9
+    assert abs(Ax.sum() / Ar.sum() - 1.0) < 2e-3
+    assert d < 0.1
