@@ -346,3 +346,119 @@ def backproject_posed(g: dict, cam: dict, y, basis: int = PILLBOX) -> np.ndarray
     gr = dict(nx=R["nx"], ny=R["ny"], nz=R["nz"], pitch=(R["hx"], R["hy"], R["hz"]))
     xr = backproject(gr, head, y, basis)
     return rotate_azimuth_adjoint(g, xr, phi).reshape(-1)
+
+
+# --------------------------------------------------------------------------
+# plenoptic camera: factorized transport through the lenslet array
+# --------------------------------------------------------------------------
+def plenoptic_maps(z_q: float, cam: dict, c_mu: float, f_mu: float):
+    """Ray maps of the factorized plenoptic model (camera-model section):
+    X^{0a} = T_{D_mu_m} (array plane -> lens), X^{0s} = (T_z R_F)^{-1}
+    (slice -> lens), and through lenslet mu (centre c_mu, focal f_mu):
+    X^{0d,mu} = X^{0a} R_mu T_{D_d_mu} (detector -> lens)."""
+    X0a = T(cam["d_mla"])
+    X0q = np.linalg.inv(T(z_q) @ R(cam["f_main"]))
+    X0d = X0a @ R(f_mu, c_mu) @ T(cam["d_mla_det"])
+    return X0a, X0q, X0d
+
+
+def _volume_axis(basis, X0p, dp, d0):
+    return detector_volume(basis, X0p, dp, d0)
+
+
+def _plenoptic_parts(g: dict, cam: dict, basis: int, ka):
+    if cam["kind"] != 1:
+        raise ValueError("the factorized model is for square-array plenoptic cameras")
+    _check_head_on(dict(cam, kind=0))
+    nx, ny, nz, dx = g["nx"], g["ny"], g["nz"], g["pitch"]
+    nu, nv, mu, mv = cam["det_nu"], cam["det_nv"], cam["mla_nu"], cam["mla_nv"]
+    k = nu // mu
+    ka = k if ka is None else ka
+    P = k * cam["pixel_pitch"]                      # lenslet pitch
+    da = P / ka                                     # array pixel
+    na_u, na_v = mu * ka, mv * ka
+    L = -cam["lens_center"][2]
+    cells, d0s, d0t = angular_cells(cam)
+    sa = (np.arange(na_u) + 0.5 - 0.5 * na_u) * da
+    ta = (np.arange(na_v) + 0.5 - 0.5 * na_v) * da
+    sj = (np.arange(nx) + 0.5 - 0.5 * nx) * dx
+    tj = (np.arange(ny) + 0.5 - 0.5 * ny) * dx
+    sd = (np.arange(nu) + 0.5 - 0.5 * nu) * cam["pixel_pitch"]
+    td = (np.arange(nv) + 0.5 - 0.5 * nv) * cam["pixel_pitch"]
+    cu = (np.arange(mu) + 0.5 - 0.5 * mu) * P
+    cv = (np.arange(mv) + 0.5 - 0.5 * mv) * P
+    own_u, own_v = np.arange(na_u) // ka, np.arange(na_v) // ka
+    inside = ((sa - cu[own_u])[None, :] ** 2 + (ta - cv[own_v])[:, None] ** 2) <= cam["r_mla"] ** 2
+    X0a = T(cam["d_mla"])
+    Va = detector_volume(basis, X0a, da, d0s) * detector_volume(basis, X0a, da, d0t)
+    _, _, X0d = plenoptic_maps(L, cam, 0.0, cam["f_mla"])
+    Vd = detector_volume(basis, X0d, cam["pixel_pitch"], d0s) * \
+        detector_volume(basis, X0d, cam["pixel_pitch"], d0t)
+    omega = (2.0 * cam["r_mla"] / cam["d_mla_det"]) ** 2
+    norm = d0s * d0t / (abs(X0d[0, 1]) ** 2 * omega)
+    stage1 = []                                      # per cell: list over slices of (Bs, Bt)
+    stage2 = []                                      # per cell: (Bs_full [nu, na_u], Bt_full [nv, na_v])
+    for (sk, tk) in cells:
+        per = []
+        for iz in range(nz):
+            zq = L + (iz + 0.5 - 0.5 * nz) * dx
+            X0q = np.linalg.inv(T(zq) @ R(cam["f_main"]))
+            Xaq = np.linalg.inv(X0a) @ X0q
+            per.append((transport_factor(basis, Xaq, X0q, sk, d0s, sa, da, sj, dx),
+                        transport_factor(basis, Xaq, X0q, tk, d0t, ta, da, tj, dx)))
+        stage1.append(per)
+        Bs2 = np.zeros((nu, na_u))
+        Bt2 = np.zeros((nv, na_v))
+        for lu in range(mu):
+            _, _, X0d_s = plenoptic_maps(L, cam, cu[lu], cam["f_mla"])
+            us = slice(lu * ka, (lu + 1) * ka)
+            Bs2[:, us] = transport_factor(basis, np.linalg.inv(X0d_s) @ X0a, X0a, sk, d0s, sd,
+                                          cam["pixel_pitch"], sa[us], da)
+        for lv in range(mv):
+            _, _, X0d_t = plenoptic_maps(L, cam, cv[lv], cam["f_mla"])
+            vs = slice(lv * ka, (lv + 1) * ka)
+            Bt2[:, vs] = transport_factor(basis, np.linalg.inv(X0d_t) @ X0a, X0a, tk, d0t, td,
+                                          cam["pixel_pitch"], ta[vs], da)
+        stage2.append((Bs2, Bt2))
+    return dict(inside=inside, Va=Va, Vd=Vd, norm=norm, dx=dx, stage1=stage1, stage2=stage2,
+                shape_a=(na_v, na_u), shape_d=(nv, nu), shape_x=(nz, ny, nx))
+
+
+def project_plenoptic(g: dict, cam: dict, x, basis: int = PILLBOX, ka: int | None = None):
+    """A x for a head-on square-array plenoptic camera in the paper's
+    factorized form: every slice is transported onto the lenslet-array plane
+    (array pixels of size pitch/ka, ka per lenslet; default the detector's
+    pixels per lenslet), the mask keeps array pixels whose centre lies in a
+    lenslet's aperture disc (the occluder rasterized on the array grid), and
+    each lenslet transports its pixels onto the detector; f^a_k = B^{as}_k
+    w_k / V^a, f^d_k = sum_mu B^{d mu}_k M_mu f^a_k / V^d.  Because each array
+    column (row) belongs to one lenslet column (row), the lenslet stage is one
+    separable banded transform per cell.  The pixel integral of the detector
+    light field is sum_k f^d_k dp^2 d0s d0t / |X^{0d}_su X^{0d}_tv| (each
+    cell integrated over the pixel's slopes); y divides it by dp^2 times the
+    solid angle (2 r_mla / D_mu_d)^2 of the lenslet's bounding square, the
+    angular domain the ray-driven operator averages over (for a single-lens
+    camera the same rule, with (2 r_main / D)^2, is the mean over cells)."""
+    Pp = _plenoptic_parts(g, cam, basis, ka)
+    x = np.asarray(x, np.float64).reshape(Pp["shape_x"])
+    y = np.zeros(Pp["shape_d"])
+    for per, (Bs2, Bt2) in zip(Pp["stage1"], Pp["stage2"]):
+        fa = np.zeros(Pp["shape_a"])
+        for iz, (Bs, Bt) in enumerate(per):
+            fa += Bt @ (Pp["dx"] * x[iz]) @ Bs.T
+        fa = fa / Pp["Va"] * Pp["inside"]
+        y += Bt2 @ fa @ Bs2.T / Pp["Vd"]
+    return (y * Pp["norm"]).reshape(-1)
+
+
+def backproject_plenoptic(g: dict, cam: dict, y, basis: int = PILLBOX, ka: int | None = None):
+    """A^T y of ``project_plenoptic`` (the stages transposed in reverse)."""
+    Pp = _plenoptic_parts(g, cam, basis, ka)
+    y = np.asarray(y, np.float64).reshape(Pp["shape_d"]) * Pp["norm"]
+    x = np.zeros(Pp["shape_x"])
+    for per, (Bs2, Bt2) in zip(Pp["stage1"], Pp["stage2"]):
+        fa = Bt2.T @ y @ Bs2 / Pp["Vd"]
+        fa = fa / Pp["Va"] * Pp["inside"]
+        for iz, (Bs, Bt) in enumerate(per):
+            x[iz] += Pp["dx"] * (Bt.T @ fa @ Bs)
+    return x.reshape(-1)

@@ -267,3 +267,73 @@ def test_rotation_stages_equal_numerical_projections():
                 out[iz, j] += r[iz, ix] * np.mean(np.abs(sx - x1[ix]) <= 0.5 * hx)
     assert np.max(np.abs(xr[:, 0, :] - out)) < 5e-3 * xr.max()
     assert xr.max() > 0.1
+
+
+# ------------------------------------------------- factorized plenoptic model
+def _mask_area_factor(cam, ka):
+    P = cam["det_nu"] // cam["mla_nu"] * cam["pixel_pitch"]
+    da = P / ka
+    c = (np.arange(ka) + 0.5 - 0.5 * ka) * da
+    inside = (c[None, :] ** 2 + c[:, None] ** 2) <= cam["r_mla"] ** 2
+    return inside.sum() * da * da / (np.pi * cam["r_mla"] ** 2)
+
+
+@pytest.mark.parametrize("basis,ka", [(X.PILLBOX, 8), (X.DIRAC, 32)])
+def test_factorized_plenoptic_agrees_with_ray_driven_oracle(orc, basis, ka):
+    # 8x8 lenslets near the axis with a 3 mm main aperture: the aperture's
+    # image through each lenslet stays inside its cell, so the own-lenslet
+    # ray model sees all the light; the factorized model's extra light is
+    # the rasterized lenslet discs' extra area (the paper's occluder mask)
+    g = W.grid(16, 6.0)
+    x = W.blobs(16, seed=2, count=4)
+    cam = W.plenoptic_camera(64, 8, (8, 8), 64)
+    cam["r_main"] = 3.0
+    y1 = X.project_plenoptic(g, cam, x, basis, ka=ka)
+    y0 = orc.project(g, [cam], x.astype(np.float64).reshape(-1))
+    ratio = y1.sum() / y0.sum() / _mask_area_factor(cam, ka)
+    assert abs(ratio - 1.0) < 0.02, ratio
+    assert np.linalg.norm(y1 - y0) / np.linalg.norm(y0) < 0.08
+
+
+def test_factorized_lenslet_stage_images_the_main_aperture():
+    # uniform light on one lenslet's array pixels, through the lenslet stage
+    # summed over cells: a ray through lens point a and lenslet point c + e
+    # reaches d = c (1 + D_d/D_m) + (D_d/D_m)(k e - a), k = 1 + D_m/D_d - D_m/f,
+    # so the lit region is the disc of radius (D_d/D_m)(|k| r_mla + r_main)
+    # around the chief point c (1 + D_d/D_m) (the Minkowski sum of the two
+    # apertures' images)
+    g = W.grid(4, 8.0)
+    cam = W.plenoptic_camera(128, 8, (16, 16), 8)
+    Pp = X._plenoptic_parts(g, cam, X.DIRAC, 16)
+    ka, P = 16, 16 * cam["pixel_pitch"]
+    lu = lv = 6                                      # an off-axis lenslet
+    fa = np.zeros(Pp["shape_a"])
+    fa[lv * ka:(lv + 1) * ka, lu * ka:(lu + 1) * ka] = 1.0
+    fa *= Pp["inside"]
+    y = sum(Bt2 @ fa @ Bs2.T for Bs2, Bt2 in Pp["stage2"])
+    c = (lu + 0.5 - 4) * P
+    e = cam["d_mla_det"] / cam["d_mla"]
+    kk = abs(1 + cam["d_mla"] / cam["d_mla_det"] - cam["d_mla"] / cam["f_mla"])
+    rad = e * (kk * cam["r_mla"] + cam["r_main"])
+    sd = (np.arange(128) + 0.5 - 64) * cam["pixel_pitch"]
+    D2 = (sd[None, :] - c * (1 + e)) ** 2 + (sd[:, None] - c * (1 + e)) ** 2
+    lit = y > 1e-9 * y.max()
+    assert np.all(np.sqrt(D2[lit]) <= rad + 2 * cam["pixel_pitch"])
+    assert np.all(lit[np.sqrt(D2) <= rad - 3 * cam["pixel_pitch"]])
+    assert lit.sum() > 0.7 * np.pi * rad ** 2 / cam["pixel_pitch"] ** 2
+
+
+def test_factorized_plenoptic_transpose():
+    g = W.grid((4, 5, 3), 8.0)
+    cam = W.plenoptic_camera(16, 4, (2, 2), 8)
+    N, M = 60, 256
+    for basis in (X.DIRAC, X.PILLBOX):
+        A = np.zeros((M, N))
+        for j in range(N):
+            e = np.zeros(N)
+            e[j] = 1.0
+            A[:, j] = X.project_plenoptic(g, cam, e, basis)
+        assert np.count_nonzero(A) > 0.02 * A.size
+        y = np.random.default_rng(3).uniform(-1, 1, M)
+        ref = A.T @ y
+        assert np.max(np.abs(X.backproject_plenoptic(g, cam, y, basis) - ref)) <= 1e-13 * np.max(np.abs(ref))
