@@ -458,6 +458,71 @@ def run_transport(args):
     return out
 
 
+def run_plenoptic_transport(args):
+    """The paper's factorized plenoptic transport (slices onto the lenslet
+    array plane per angular cell, the aperture mask, each lenslet onto the
+    detector) for the default benchmark's camera: 128^3 flame at 1.25 mm,
+    1024^2 pixels behind 64^2 lenslets, 4x4 pillbox cells; one A x + one A^T y
+    per step.  Beside it, the normalized difference to the ray-driven
+    operator's image (8x8 rays per pixel, 256 samples per ray)."""
+    import torch
+
+    from paper_1812_03358_amd import ltm, workloads as W
+
+    n, K = 128, 4
+    g = W.grid(n, 1.25)
+    cam = W.plenoptic_camera(1024, 64, (K, K), 1)
+    x = torch.from_numpy(W.flame(n, 2).reshape(-1)).cuda()
+    t0 = time.perf_counter()
+    op = ltm.Transport(g, cam, ltm.BASIS_PILLBOX)
+    t_tables = time.perf_counter() - t0
+    y = op.project(x)
+    xt = torch.empty_like(x)
+    for _ in range(args.warmup):
+        op.project(x, y)
+        op.backproject(y, xt)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    f_ms = a_ms = 0.0
+    for _ in range(args.steps):
+        ev[0].record()
+        op.project(x, y)
+        ev[1].record()
+        op.backproject(y, xt)
+        ev[2].record()
+        torch.cuda.synchronize()
+        f_ms += ev[0].elapsed_time(ev[1])
+        a_ms += ev[1].elapsed_time(ev[2])
+    f_ms /= args.steps
+    a_ms /= args.steps
+    ms = f_ms + a_ms
+    # algorithmic HBM bytes per direction: input and output once, each of the
+    # three FP32 intermediates written once and read once
+    r = cam["r_main"]
+    d0 = 2.0 * r / K
+    cells = sum(((i + 0.5) * d0 - r) ** 2 + ((j + 0.5) * d0 - r) ** 2 <= r * r
+                for i in range(K) for j in range(K))
+    inter = n * K * 1024 * n + 2 * cells * 1024 * 1024
+    nbytes = 4 * (n ** 3 + 1024 ** 2) + 2 * 4 * inter
+    ray = ltm.Plan(g, [W.plenoptic_camera(1024, 64, (8, 8), 256)])
+    yr = ray.project(x).double()
+    nsd = float(torch.linalg.norm(y.double() - yr) / torch.linalg.norm(yr))
+    out = base_record(args, 1000.0 / ms, ms,
+                      "plenoptic_transport_128: paper's factorized plenoptic transport, pillbox "
+                      "basis, 1024^2 behind 64^2 lenslets head-on, 128^3 flame at 1.25 mm, 4x4 "
+                      "angular cells; one A x + one A^T y per step",
+                      {"bands": op.bands(), "table_build_s": round(t_tables, 3), "cells": cells})
+    out["metric"] = "transport A x + A^T y pairs/s"
+    out["unit"] = "pairs/s"
+    gbs = 2 * nbytes / (ms * 1e-3) / 1e9
+    out["roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
+    out["ms_project"] = round(f_ms, 4)
+    out["ms_backproject"] = round(a_ms, 4)
+    out["nsd_vs_ray_driven_8x8"] = nsd
+    return out
+
+
 def run_warm_start(args):
     """Learned warm start (2 plenoptic cameras at 0/90 deg, 128^3): train the
     network on projector-generated pairs for a time budget, then time the
@@ -505,7 +570,8 @@ def main():
     ap.add_argument("--workload", default="plenoptic_128",
                     choices=["plenoptic_128", "thin_lens_32", "differentiable_256", "batched_48",
                              "recon_plenoptic_128", "recon_three_camera_100", "warm_start_128",
-                             "hex_plenoptic_100", "transport_100"])
+                             "hex_plenoptic_100", "transport_100",
+                             "plenoptic_transport_128"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", action="store_true")
@@ -544,6 +610,8 @@ def main():
                          "A^T y per step")
     elif args.workload == "transport_100":
         out = run_transport(args)
+    elif args.workload == "plenoptic_transport_128":
+        out = run_plenoptic_transport(args)
     elif args.workload == "batched_48":
         out = run_batched(args)
     elif args.workload == "warm_start_128":

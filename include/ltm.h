@@ -392,7 +392,24 @@ ltm_status ltm_nn_add(float* a, const float* b, uint64_t n, void* stream);
  * paper's sqrt(V^d) sum over cells replaced by the mean over cells, a global
  * scale).  A^T uses the same FP32 entries.  Accumulation is FP64 per output.
  * The library evaluates the entries in FP64 once, at bind time, into banded
- * FP32 tables in the workspace. */
+ * FP32 tables in the workspace.
+ *
+ * A head-on square-array plenoptic camera (LTM_PLENOPTIC, phi = 0) takes
+ * the paper's factorized plenoptic model instead: every slice is transported
+ * onto the lenslet-array plane (d_mla behind the main lens; array pixels of
+ * the detector's pitch, det_nu / mla_nu per lenslet) per angular cell; the
+ * aperture mask keeps array pixels whose centre lies inside their lenslet's
+ * disc of radius r_mla (the occluder rasterized on the array grid), scaled by
+ * 1 / V^a; each lenslet then transports its own pixels onto the detector
+ * d_mla_det behind it (lenslet focal length f_mla).  The array stage is
+ * separable per cell, so both stages are banded s and t factor tables.
+ * y = norm sum_cells B^d_cell (mask . f^a_cell) / V^d with norm = d0s d0t /
+ * ((d_mla + d_mla_det - d_mla d_mla_det / f_mla)^2 (2 r_mla / d_mla_det)^2):
+ * the pixel integral over dp^2 times the solid angle of the lenslet's
+ * bounding square.  Workspace: the tables plus three FP32 intermediates,
+ * nz * rays_v * det_nv * nx (slices filtered along t), cells * det_nv *
+ * det_nu (the masked array-plane light field), and the same again (after
+ * the lenslet t stage). */
 enum { LTM_BASIS_DIRAC = 0u, LTM_BASIS_PILLBOX = 1u };
 
 typedef struct ltm_xport ltm_xport;
@@ -401,7 +418,7 @@ ltm_status ltm_xport_create(const ltm_grid* grid, const ltm_camera* camera, uint
                             ltm_xport** out);
 void ltm_xport_destroy(ltm_xport* t);
 /* Workspace for the banded tables and the nz * rays_v * det_nv * nx FP32
- * intermediate of the two filtering passes. */
+ * intermediate of the two filtering passes (plenoptic: the three above). */
 ltm_status ltm_xport_workspace_bytes(const ltm_xport* t, uint64_t* bytes);
 /* Binds caller-owned device memory (>= workspace_bytes, 256-byte aligned)
  * and uploads the tables; synchronizes the stream. */
@@ -411,7 +428,8 @@ ltm_status ltm_xport_project(ltm_xport* t, const float* x, float* y, void* strea
 /* x = A^T y (overwrites x). */
 ltm_status ltm_xport_backproject(ltm_xport* t, const float* y, float* x, void* stream);
 /* Band widths of the four tables: t-factor rows, s-factor rows (cells of
- * one row summed), and their transposes. */
+ * one row summed), and their transposes; for the plenoptic model those of
+ * the slice-to-array stage (t, s, s transposed, t transposed). */
 ltm_status ltm_xport_bands(const ltm_xport* t, uint32_t bands[4]);
 
 #ifdef __cplusplus

@@ -33,6 +33,13 @@ struct ltm_xport {
     bool rot = false;
     int nxr = 0, nyr = 0, nzr = 0;          // transport grid (rotated, or the natural one)
     Band ez, ezt, ex, ext;
+    // factorized plenoptic model (square lenslet array)
+    bool plen = false;
+    int na_u = 0, na_v = 0, ncells = 0, ks = 0;
+    std::vector<int32_t> cell_ks, cell_kt, cell_first;
+    std::vector<float> mask;
+    Band bt1, bs1, bt2, bs2, bt1t, bs1t, bt2t, bs2t;
+    uint64_t off_pl[20] = {};
     uint64_t off_bt_s = 0, off_bt_w = 0, off_cs_s = 0, off_cs_w = 0, off_cst_s = 0, off_cst_w = 0,
              off_btt_s = 0, off_btt_w = 0, off_mid = 0, ws_bytes = 0;
     uint64_t off_ez_s = 0, off_ez_w = 0, off_ezt_s = 0, off_ezt_w = 0, off_ex_s = 0, off_ex_w = 0,
@@ -53,10 +60,52 @@ struct Kernel1D {
     double h, mag;
 };
 
+// One axis of an affine ray map (s' = ss s + su u + bar), or the 3x3 form
+// on (s, u, 1) for compositions.
+struct Aff {
+    double m[3][3];
+};
+
+Aff aff_mul(const Aff& a, const Aff& b)
+{
+    Aff r{};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            for (int k = 0; k < 3; ++k) r.m[i][j] += a.m[i][k] * b.m[k][j];
+    return r;
+}
+
+Aff aff_inv(const Aff& a)
+{
+    // [[A, t], [0, 1]]^-1 = [[A^-1, -A^-1 t], [0, 1]]
+    const double det = a.m[0][0] * a.m[1][1] - a.m[0][1] * a.m[1][0];
+    Aff r{};
+    r.m[0][0] = a.m[1][1] / det;
+    r.m[0][1] = -a.m[0][1] / det;
+    r.m[1][0] = -a.m[1][0] / det;
+    r.m[1][1] = a.m[0][0] / det;
+    r.m[0][2] = -(r.m[0][0] * a.m[0][2] + r.m[0][1] * a.m[1][2]);
+    r.m[1][2] = -(r.m[1][0] * a.m[0][2] + r.m[1][1] * a.m[1][2]);
+    r.m[2][2] = 1.0;
+    return r;
+}
+
+Aff aff_T(double d) { return Aff{{{1.0, d, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}}}; }
+Aff aff_R(double f, double c) { return Aff{{{1.0, 0.0, 0.0}, {-1.0 / f, 1.0, c / f}, {0.0, 0.0, 1.0}}}; }
+
+Kernel1D kernel_affine(int basis, const Aff& Xpq, const Aff& X0q, double sk, double d0, double dp);
+
 Kernel1D kernel_of(int basis, double z, double D, double F, double sk, double d0, double dp)
 {
-    const double qss = 1.0, qsu = -z, qbar = 0.0;                  // X^{0q}
-    const double pss = 1.0 - D / F, psu = D * z / F - z - D, pbar = 0.0;  // X^{pq}
+    Aff X0q{{{1.0, -z, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}}};
+    Aff Xpq{{{1.0 - D / F, D * z / F - z - D, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}}};
+    return kernel_affine(basis, Xpq, X0q, sk, d0, dp);
+}
+
+Kernel1D kernel_affine(int basis, const Aff& Xpq, const Aff& X0q, double sk, double d0, double dp)
+{
+    const double qss = X0q.m[0][0], qsu = X0q.m[0][1], qbar = X0q.m[0][2];
+    const double pss = Xpq.m[0][0], psu = Xpq.m[0][1], pbar = Xpq.m[0][2];
     Kernel1D k{};
     k.basis = basis;
     if (basis == LTM_BASIS_DIRAC) {
@@ -111,6 +160,28 @@ void factor_row(const Kernel1D& k, double si, double dq, int n, double scale,
         const double v = k.h * (G(k, a + dq) - G(k, a)) * scale;
         if (v != 0.0) out.emplace_back(j, v);
     }
+}
+
+// Entries of one factor row over source cells [j0, j1) of size dq whose
+// left edges are at (j - n/2) dq (a sub-block of a lattice of n cells).
+void factor_row_block(const Kernel1D& k, double si, double dq, int n, int j0, int j1, double scale,
+                      std::vector<std::pair<int, double>>& out)
+{
+    const double c = k.mag * si;
+    for (int j = j0; j < j1; ++j) {
+        const double a = (j - 0.5 * n) * dq - c;
+        const double v = k.h * (G(k, a + dq) - G(k, a)) * scale;
+        if (v != 0.0) out.emplace_back(j, v);
+    }
+}
+
+double axis_volume_affine(int basis, const Aff& X0p, double dp, double d0)
+{
+    const double ss = X0p.m[0][0], su = X0p.m[0][1];
+    if (basis == LTM_BASIS_DIRAC) return dp * std::fabs(d0 / su);
+    const double m = std::max(d0 / (2.0 * std::fabs(su)), dp * std::fabs(ss / su) / 2.0);
+    const double h = std::min(dp, d0 / std::fabs(ss));
+    return 2.0 * m * h;
 }
 
 double axis_volume(int basis, double D, double dp, double d0)
@@ -202,6 +273,140 @@ Rows shear_rows(int n_out, int n_in, double h, double shift, double width)
 
 using namespace ltm;
 
+namespace {
+
+// The factorized plenoptic model (camera-model section, plenoptic camera):
+// slices -> array plane per angular cell, the rasterized aperture mask, then
+// each lenslet -> detector.  Array pixels: the detector's pixel pitch, k per
+// lenslet.  Tables hold the table entries with the slice thickness folded into
+// the s factor of stage 1 and the measurement normalization (the pixel
+// integral divided by dp^2 times the lenslet bounding square's solid angle
+// (2 r / D_d)^2, over V^d) into the s factor of stage 2.
+ltm_status create_plenoptic(const ltm_grid* g, const ltm_camera* c, uint32_t basis, double L,
+                            ltm_xport** out)
+{
+    const int nx = (int)g->nx, ny = (int)g->ny, nz = (int)g->nz;
+    const int nu = (int)c->det_nu, nv = (int)c->det_nv, mu = (int)c->mla_nu, mv = (int)c->mla_nv;
+    const int ka = nu / mu;
+    const int Ks = (int)c->rays_u, Kt = (int)c->rays_v;
+    const double dx = g->pitch_mm, dp = c->pixel_pitch_mm, P = ka * dp, da = dp;
+    const double r = c->r_main_mm, d0s = 2.0 * r / Ks, d0t = 2.0 * r / Kt;
+    const double Dm = c->d_mla_mm, Dd = c->d_mla_det_mm;
+    if (!(L - 0.5 * nz * dx > 0.0)) return fail(LTM_ERR_INVALID, "every slice must lie in front of the lens");
+    const uint64_t m1 = (uint64_t)nz * Kt * nv * (uint64_t)nx;
+    if (m1 > (1ull << 34) || (uint64_t)Ks * Kt * nv * (uint64_t)nu > (1ull << 34))
+        return fail(LTM_ERR_INVALID, "intermediates larger than 2^34 values");
+    ltm_xport* t = new ltm_xport();
+    t->grid = *g;
+    t->cam = *c;
+    t->basis = basis;
+    t->plen = true;
+    t->kt = Kt;
+    t->ks = Ks;
+    t->na_u = nu;
+    t->na_v = nv;
+    const int na_u = nu, na_v = nv;
+    // active cells, row by row
+    t->cell_first.push_back(0);
+    for (int kt = 0; kt < Kt; ++kt) {
+        const double tk = (kt + 0.5) * d0t - r;
+        for (int ks = 0; ks < Ks; ++ks) {
+            const double sk = (ks + 0.5) * d0s - r;
+            if (sk * sk + tk * tk > r * r) continue;
+            t->cell_ks.push_back(ks);
+            t->cell_kt.push_back(kt);
+        }
+        t->cell_first.push_back((int32_t)t->cell_ks.size());
+    }
+    t->ncells = (int)t->cell_ks.size();
+    const Aff X0a = aff_T(Dm);
+    const Aff X0d = aff_mul(aff_mul(X0a, aff_R(c->f_mla_mm, 0.0)), aff_T(Dd));
+    const double Va = axis_volume_affine((int)basis, X0a, da, d0s) * axis_volume_affine((int)basis, X0a, da, d0t);
+    const double Vd = axis_volume_affine((int)basis, X0d, dp, d0s) * axis_volume_affine((int)basis, X0d, dp, d0t);
+    const double omega = (2.0 * c->r_mla_mm / Dd) * (2.0 * c->r_mla_mm / Dd);
+    const double norm = d0s * d0t / (X0d.m[0][1] * X0d.m[0][1] * omega);
+    // mask: array pixel centre inside its lenslet's aperture disc, over V^a
+    t->mask.assign((size_t)na_v * na_u, 0.0f);
+    for (int va = 0; va < na_v; ++va)
+        for (int ua = 0; ua < na_u; ++ua) {
+            const double sa = (ua + 0.5 - 0.5 * na_u) * da, ta = (va + 0.5 - 0.5 * na_v) * da;
+            const double cs = (ua / ka + 0.5 - 0.5 * mu) * P, ct = (va / ka + 0.5 - 0.5 * mv) * P;
+            if ((sa - cs) * (sa - cs) + (ta - ct) * (ta - ct) <= c->r_mla_mm * c->r_mla_mm)
+                t->mask[(size_t)va * na_u + ua] = (float)(1.0 / Va);
+        }
+    // stage 1: per (slice, kt) t factor and per (slice, ks) s factor
+    std::vector<Rows> bt1, bs1;
+    for (int iz = 0; iz < nz; ++iz) {
+        const double z = L + (iz + 0.5 - 0.5 * nz) * dx;
+        const Aff X0q = aff_inv(aff_mul(aff_T(z), aff_R(c->f_main_mm, 0.0)));
+        const Aff Xaq = aff_mul(aff_inv(X0a), X0q);
+        for (int kt = 0; kt < Kt; ++kt) {
+            const Kernel1D k1 = kernel_affine((int)basis, Xaq, X0q, (kt + 0.5) * d0t - r, d0t, da);
+            Rows rows(na_v);
+            for (int va = 0; va < na_v; ++va) factor_row(k1, (va + 0.5 - 0.5 * na_v) * da, dx, ny, 1.0, rows[va]);
+            bt1.push_back(std::move(rows));
+        }
+        for (int ks = 0; ks < Ks; ++ks) {
+            const Kernel1D k1 = kernel_affine((int)basis, Xaq, X0q, (ks + 0.5) * d0s - r, d0s, da);
+            Rows rows(na_u);
+            for (int ua = 0; ua < na_u; ++ua) factor_row(k1, (ua + 0.5 - 0.5 * na_u) * da, dx, nx, dx, rows[ua]);
+            bs1.push_back(std::move(rows));
+        }
+    }
+    // stage 2: per angular column / row, each lenslet's block of array pixels
+    // onto the detector (every lenslet whose block meets the kernel's support)
+    auto stage2 = [&](int K, double d0, int nd, int nl, std::vector<Rows>& outv, double scale) {
+        for (int kk = 0; kk < K; ++kk) {
+            const double sk = (kk + 0.5) * d0 - r;
+            std::vector<Kernel1D> kern(nl);
+            for (int l = 0; l < nl; ++l) {
+                const double cl = (l + 0.5 - 0.5 * nl) * P;
+                const Aff X0dl = aff_mul(aff_mul(X0a, aff_R(c->f_mla_mm, cl)), aff_T(Dd));
+                kern[l] = kernel_affine((int)basis, aff_mul(aff_inv(X0dl), X0a), X0a, sk, d0, dp);
+            }
+            Rows rows(nd);
+            for (int i = 0; i < nd; ++i) {
+                const double si = (i + 0.5 - 0.5 * nd) * dp;
+                for (int l = 0; l < nl; ++l) {
+                    const double c0 = kern[l].mag * si;
+                    const double lo = (l * ka - 0.5 * nl * ka) * da - c0, hi = lo + ka * da;
+                    if (hi <= kern[l].tau[0] || lo >= kern[l].tau[3]) continue;
+                    factor_row_block(kern[l], si, da, nl * ka, l * ka, (l + 1) * ka, scale, rows[i]);
+                }
+            }
+            outv.push_back(std::move(rows));
+        }
+    };
+    std::vector<Rows> bt2, bs2;
+    stage2(Kt, d0t, nv, mv, bt2, 1.0);
+    stage2(Ks, d0s, nu, mu, bs2, norm / Vd);
+    pack(bt1, na_v, t->bt1);
+    pack(bs1, na_u, t->bs1);
+    pack(bt2, nv, t->bt2);
+    pack(bs2, nu, t->bs2);
+    transpose(t->bt1, nz * Kt, ny, t->bt1t);
+    transpose(t->bs1, nz * Ks, nx, t->bs1t);
+    transpose(t->bt2, Kt, na_v, t->bt2t);
+    transpose(t->bs2, Ks, na_u, t->bs2t);
+    uint64_t off = 0;
+    auto place = [&](int i, uint64_t bytes) { t->off_pl[i] = off; off = align256(off + bytes); };
+    const ltm_xport::Band* bands[8] = {&t->bt1, &t->bs1, &t->bt2, &t->bs2, &t->bt1t, &t->bs1t, &t->bt2t, &t->bs2t};
+    for (int i = 0; i < 8; ++i) {
+        place(2 * i, bands[i]->start.size() * 4);
+        place(2 * i + 1, bands[i]->w.size() * 4);
+    }
+    place(16, (t->cell_ks.size() + t->cell_kt.size() + t->cell_first.size()) * 4);
+    place(17, t->mask.size() * 4);
+    place(18, m1 * 4 + (uint64_t)t->ncells * na_v * na_u * 4);      // M1, then FA
+    place(19, (uint64_t)t->ncells * nv * na_u * 4);                 // M2
+    t->ws_bytes = off;
+    *out = t;
+    clear_error();
+    return LTM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 ltm_status ltm_xport_create(const ltm_grid* g, const ltm_camera* c, uint32_t basis, ltm_xport** out)
@@ -216,8 +421,8 @@ ltm_status ltm_xport_create(const ltm_grid* g, const ltm_camera* c, uint32_t bas
     one.rays_u = one.rays_v = 1;
     ltm_status st = validate_cameras(g, &one, 1);
     if (st != LTM_OK) return st;
-    if (c->kind != LTM_SINGLE_LENS)
-        return fail(LTM_ERR_UNSUPPORTED, "the transport operator models single-lens cameras");
+    if (c->kind != LTM_SINGLE_LENS && c->kind != LTM_PLENOPTIC)
+        return fail(LTM_ERR_UNSUPPORTED, "the transport operator models single-lens and square-array plenoptic cameras");
     // pose: azimuth phi about the grid's y axis, |phi| <= 45 deg, the lens on
     // the camera axis through the grid centre
     const double* es = c->axes;
@@ -235,6 +440,10 @@ ltm_status ltm_xport_create(const ltm_grid* g, const ltm_camera* c, uint32_t bas
             return fail(LTM_ERR_UNSUPPORTED, "the transport operator needs the lens on the camera axis through the grid centre");
     const double cphi = std::cos(phi), sphi = std::sin(phi);
     const bool rot = std::fabs(sphi) > 1e-15;
+    if (c->kind == LTM_PLENOPTIC) {
+        if (rot) return fail(LTM_ERR_UNSUPPORTED, "the factorized plenoptic transport needs a head-on camera");
+        return create_plenoptic(g, c, basis, L, out);
+    }
     const double sa = -sphi * cphi, sb = sphi / cphi;           // S_z: z += sa x, S_x: x += sb z
     const double d = g->pitch_mm;
     const double hx = rot ? d / cphi : d, hy = d, hz = rot ? d * cphi : d;
@@ -362,10 +571,11 @@ ltm_status ltm_xport_workspace_bytes(const ltm_xport* t, uint64_t* bytes)
 ltm_status ltm_xport_bands(const ltm_xport* t, uint32_t bands[4])
 {
     if (!t || !bands) return fail(LTM_ERR_INVALID, "null argument");
-    bands[0] = (uint32_t)t->bt.width;
-    bands[1] = (uint32_t)t->cs.width;
-    bands[2] = (uint32_t)t->cst.width;
-    bands[3] = (uint32_t)t->btt.width;
+    const bool p = t->plen;
+    bands[0] = (uint32_t)(p ? t->bt1.width : t->bt.width);
+    bands[1] = (uint32_t)(p ? t->bs1.width : t->cs.width);
+    bands[2] = (uint32_t)(p ? t->bs1t.width : t->cst.width);
+    bands[3] = (uint32_t)(p ? t->bt1t.width : t->btt.width);
     return LTM_OK;
 }
 
@@ -393,7 +603,23 @@ ltm_status ltm_xport_bind_workspace(ltm_xport* t, void* ws, uint64_t bytes, void
         {t->off_ex_w, t->ex.w.data(), t->ex.w.size() * 4},
         {t->off_ext_s, t->ext.start.data(), t->ext.start.size() * 4},
         {t->off_ext_w, t->ext.w.data(), t->ext.w.size() * 4}};
-    for (const Up& u : ups) {
+    std::vector<Up> all;
+    if (t->plen) {
+        const ltm_xport::Band* bands[8] = {&t->bt1, &t->bs1, &t->bt2, &t->bs2,
+                                           &t->bt1t, &t->bs1t, &t->bt2t, &t->bs2t};
+        for (int i = 0; i < 8; ++i) {
+            all.push_back({t->off_pl[2 * i], bands[i]->start.data(), bands[i]->start.size() * 4});
+            all.push_back({t->off_pl[2 * i + 1], bands[i]->w.data(), bands[i]->w.size() * 4});
+        }
+        const size_t nc = t->cell_ks.size(), nf = t->cell_first.size();
+        all.push_back({t->off_pl[16], t->cell_ks.data(), nc * 4});
+        all.push_back({t->off_pl[16] + nc * 4, t->cell_kt.data(), nc * 4});
+        all.push_back({t->off_pl[16] + 2 * nc * 4, t->cell_first.data(), nf * 4});
+        all.push_back({t->off_pl[17], t->mask.data(), t->mask.size() * 4});
+    } else {
+        all.assign(std::begin(ups), std::end(ups));
+    }
+    for (const Up& u : all) {
         if (u.n == 0) continue;
         hipError_t e = hipMemcpyAsync(base + u.off, u.src, u.n, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "upload transport tables");
@@ -459,6 +685,49 @@ ltm::ShearDev shear_of(const ltm_xport* t)
     return r;
 }
 
+ltm::PlenDev plen_of(const ltm_xport* t)
+{
+    ltm::PlenDev d{};
+    d.nx = (int)t->grid.nx;
+    d.ny = (int)t->grid.ny;
+    d.nz = (int)t->grid.nz;
+    d.na_u = t->na_u;
+    d.na_v = t->na_v;
+    d.nu = (int)t->cam.det_nu;
+    d.nv = (int)t->cam.det_nv;
+    d.ks = t->ks;
+    d.kt = t->kt;
+    d.cells = t->ncells;
+    d.row_cells_max = 0;
+    for (size_t k = 0; k + 1 < t->cell_first.size(); ++k)
+        d.row_cells_max = std::max(d.row_cells_max, t->cell_first[k + 1] - t->cell_first[k]);
+    const int32_t* cl = reinterpret_cast<const int32_t*>(t->ws + t->off_pl[16]);
+    d.cell_ks = cl;
+    d.cell_kt = cl + t->ncells;
+    d.cell_first = cl + 2 * t->ncells;
+    auto band = [&](const ltm_xport::Band& b, int i) {
+        ltm::BandDev q;
+        q.start = reinterpret_cast<const int32_t*>(t->ws + t->off_pl[2 * i]);
+        q.w = reinterpret_cast<const float*>(t->ws + t->off_pl[2 * i + 1]);
+        q.rows = b.rows;
+        q.width = b.width;
+        return q;
+    };
+    d.bt1 = band(t->bt1, 0);
+    d.bs1 = band(t->bs1, 1);
+    d.bt2 = band(t->bt2, 2);
+    d.bs2 = band(t->bs2, 3);
+    d.bt1t = band(t->bt1t, 4);
+    d.bs1t = band(t->bs1t, 5);
+    d.bt2t = band(t->bt2t, 6);
+    d.bs2t = band(t->bs2t, 7);
+    d.mask = reinterpret_cast<const float*>(t->ws + t->off_pl[17]);
+    d.m1 = reinterpret_cast<float*>(t->ws + t->off_pl[18]);
+    d.fa = d.m1 + (size_t)d.nz * d.kt * d.na_v * d.nx;
+    d.m2 = reinterpret_cast<float*>(t->ws + t->off_pl[19]);
+    return d;
+}
+
 }  // namespace
 
 extern "C" {
@@ -469,7 +738,9 @@ ltm_status ltm_xport_project(ltm_xport* t, const float* x, float* y, void* strea
     if (!t->bound) return fail(LTM_ERR_WORKSPACE, "transport operator has no bound workspace");
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
-    if (t->rot) {
+    if (t->plen) {
+        e = launch_plen_project(plen_of(t), x, y, s);
+    } else if (t->rot) {
         const ltm::ShearDev r = shear_of(t);
         e = launch_shear_forward(r, x, s);
         if (e == hipSuccess) e = launch_xport_project(dev_of(t), r.xr, y, s);
@@ -485,7 +756,9 @@ ltm_status ltm_xport_backproject(ltm_xport* t, const float* y, float* x, void* s
     if (!t->bound) return fail(LTM_ERR_WORKSPACE, "transport operator has no bound workspace");
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
-    if (t->rot) {
+    if (t->plen) {
+        e = launch_plen_backproject(plen_of(t), y, x, s);
+    } else if (t->rot) {
         const ltm::ShearDev r = shear_of(t);
         e = launch_xport_backproject(dev_of(t), y, r.xr, s);
         if (e == hipSuccess) e = launch_shear_adjoint(r, x, s);

@@ -40,6 +40,33 @@ struct ShearDev {
     float* xr;     // rotated volume
 };
 
+// Factorized plenoptic transport (square lenslet array): slices -> array
+// plane per angular cell, the aperture mask, then each lenslet -> detector.
+// Cells are listed row by row (kt outer); cell_first[kt] .. cell_first[kt+1]
+// are the active cells of angular row kt.
+struct PlenDev {
+    int nx, ny, nz;          // grid
+    int na_u, na_v;          // array-plane pixels
+    int nu, nv;              // detector
+    int ks, kt, cells;       // angular columns, rows, active cells
+    int row_cells_max;       // most active cells in one angular row
+    const int32_t* cell_ks;
+    const int32_t* cell_kt;
+    const int32_t* cell_first;
+    BandDev bt1;   // per (slice, kt): rows = array rows,    columns = voxel rows
+    BandDev bs1;   // per (slice, ks): rows = array columns, columns = voxel columns (x dz)
+    BandDev bt2;   // per kt:          rows = detector rows, columns = array rows
+    BandDev bs2;   // per ks:          rows = detector cols, columns = array columns (x norm / V^d)
+    BandDev bt1t, bs1t, bt2t, bs2t;   // transposes
+    const float* mask;       // array pixel inside its lenslet's disc, / V^a
+    float* m1;               // [slice][kt][array row][x]
+    float* fa;               // [cell][array row][array col]
+    float* m2;               // [cell][detector row][array col]
+};
+
+hipError_t launch_plen_project(const PlenDev& d, const float* x, float* y, hipStream_t s);
+hipError_t launch_plen_backproject(const PlenDev& d, const float* y, float* x, hipStream_t s);
+
 hipError_t launch_xport_project(const XportDev& d, const float* x, float* y, hipStream_t s);
 hipError_t launch_xport_backproject(const XportDev& d, const float* y, float* x, hipStream_t s);
 hipError_t launch_shear_forward(const ShearDev& r, const float* x, hipStream_t s);

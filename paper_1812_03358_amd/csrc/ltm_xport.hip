@@ -9,6 +9,10 @@
 // transposed tables in the opposite order.  Every output has one writer
 // (no atomics): the minor passes write one intermediate value per thread and
 // the major passes accumulate a whole output in FP64 registers.
+//
+// A posed camera wraps these passes in the rotation's z and x shears; the
+// factorized plenoptic model chains two such separable stages (slices onto
+// the lenslet-array plane, the mask, each lenslet onto the detector).
 #include <algorithm>
 
 #include "ltm_xport.h"
@@ -377,6 +381,475 @@ hipError_t launch_xport_backproject(const XportDev& d, const float* y, float* x,
     if (e != hipSuccess) return e;
     const size_t nx = (size_t)d.nz * d.ny * d.nx;
     hipLaunchKernelGGL(k_minor_adj, dim3(grid_for(nx)), dim3(kBlock), 0, s, d, x);
+    return hipGetLastError();
+}
+
+
+// ------------------------------------------------ factorized plenoptic model
+namespace {
+
+__device__ __forceinline__ double band_dot(const BandDev& b, size_t tab, int row, const float* src,
+                                           size_t stride, int ncols)
+{
+    const int st = b.start[tab * b.rows + row];
+    const float* w = b.w + tab * b.width * (size_t)b.rows + row;
+    double acc = 0.0;
+    for (int k = 0; k < b.width; ++k) {
+        const int c = st + k;
+        if (c < ncols) acc += (double)(w[(size_t)k * b.rows] * src[(size_t)c * stride]);
+    }
+    return acc;
+}
+
+// FA[c][va][ua] = mask[va][ua] * sum_iz sum_k bs1[iz, ks_c][ua][k] M1[iz][kt_c][va][st + k]
+__global__ __launch_bounds__(kBlock) void k_pl_major1(PlenDev d)
+{
+    const size_t total = (size_t)d.cells * d.na_v * d.na_u;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * kBlock) {
+        const int ua = (int)(i % d.na_u);
+        const size_t q = i / d.na_u;
+        const int va = (int)(q % d.na_v);
+        const int c = (int)(q / d.na_v);
+        const int ks = d.cell_ks[c], kt = d.cell_kt[c];
+        double acc = 0.0;
+        for (int iz = 0; iz < d.nz; ++iz) {
+            const float* row = d.m1 + (((size_t)iz * d.kt + kt) * d.na_v + va) * d.nx;
+            acc += band_dot(d.bs1, (size_t)iz * d.ks + ks, ua, row, 1, d.nx);
+        }
+        d.fa[i] = (float)acc * d.mask[(size_t)va * d.na_u + ua];
+    }
+}
+
+// k_pl_major1 with the table width W fixed at compile time and the slice
+// loop unrolled, so the loads of several slices are in flight together.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_pl_major1_w(PlenDev d)
+{
+    const size_t total = (size_t)d.cells * d.na_v * d.na_u;
+    const size_t zstride = (size_t)d.kt * d.na_v * d.nx;
+    const size_t sstride = (size_t)d.ks * d.na_u;             // start: next slice
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * kBlock) {
+        const int ua = (int)(i % d.na_u);
+        const size_t q = i / d.na_u;
+        const int va = (int)(q % d.na_v);
+        const int c = (int)(q / d.na_v);
+        const int ks = d.cell_ks[c], kt = d.cell_kt[c];
+        const float* row = d.m1 + ((size_t)kt * d.na_v + va) * d.nx;
+        const int32_t* st = d.bs1.start + (size_t)ks * d.na_u + ua;
+        const float* w = d.bs1.w + (size_t)ks * W * d.na_u + ua;
+        double acc = 0.0;
+#pragma unroll 8
+        for (int iz = 0; iz < d.nz; ++iz) {
+            const int s0 = st[iz * sstride];
+            const float* wz = w + iz * sstride * W;
+            const float* rz = row + iz * zstride;
+#pragma unroll
+            for (int k = 0; k < W; ++k)
+                acc += (double)(wz[(size_t)k * d.na_u] * rz[min(s0 + k, d.nx - 1)]);
+        }
+        d.fa[i] = (float)acc * d.mask[(size_t)va * d.na_u + ua];
+    }
+}
+
+// R consecutive floats of an LDS row group (16-, 8- or 4-byte aligned).
+template <int R>
+__device__ __forceinline__ void lds_rows(const float* p, float (&v)[R])
+{
+    if constexpr (R % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < R; i += 4) {
+            const float4 q = *reinterpret_cast<const float4*>(p + i);
+            v[i] = q.x; v[i + 1] = q.y; v[i + 2] = q.z; v[i + 3] = q.w;
+        }
+    } else if constexpr (R == 2) {
+        const float2 q = *reinterpret_cast<const float2*>(p);
+        v[0] = q.x; v[1] = q.y;
+    } else {
+        v[0] = p[0];
+    }
+}
+
+// k_pl_major1 with the intermediate staged in LDS: a workgroup of kBlockF
+// threads takes R array rows of one angular row kt and kBlockF output columns
+// of that row (columns run over the row's cells, then the array columns); per
+// chunk of zc slices it stages the R rows of every slice once (coalesced, the
+// R rows of one voxel column adjacent so one LDS read serves all R, W - 1
+// zero columns past the last so the band needs no clamp), and a thread
+// applies its column's band weights, loaded once per slice, to the R staged
+// rows.  Sums: FP32 over the terms of kGroup consecutive slices, FP64 across
+// groups.  W is the table's width.
+constexpr int kBlockF = 1024;
+constexpr int kGroup = 4;
+
+template <int R, int W>
+__global__ __launch_bounds__(kBlockF) void k_pl_major1_lds(PlenDev d, int zc, int ncb)
+{
+    extern __shared__ float4 ms4[];
+    float* ms = reinterpret_cast<float*>(ms4);             // [slice of the chunk][nx + W - 1][R]
+    const int nvb = (d.na_v + R - 1) / R;
+    const int kt = blockIdx.x / (nvb * ncb);
+    const int rem = blockIdx.x % (nvb * ncb);
+    const int va0 = (rem / ncb) * R;
+    const int j = (rem % ncb) * kBlockF + threadIdx.x;
+    const int nr = min(R, d.na_v - va0);
+    const int c0 = d.cell_first[kt];
+    const int ncols = (d.cell_first[kt + 1] - c0) * d.na_u;
+    if ((rem % ncb) * kBlockF >= ncols) return;            // uniform over the workgroup
+    const bool live = j < ncols;
+    const int ua = live ? j % d.na_u : 0;
+    const int ks = live ? d.cell_ks[c0 + j / d.na_u] : 0;
+    const int pitch = (d.nx + W - 1) * R;                  // floats per staged slice
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0;
+    // 32-bit table offsets (the launcher checks the tables' sizes)
+    const int sstep = d.ks * d.na_u;
+    const int so = ks * d.na_u + ua;
+    const int lane = threadIdx.x & 63;
+    for (int z0 = 0; z0 < d.nz; z0 += zc) {
+        const int nzc = min(zc, d.nz - z0);
+        __syncthreads();                                   // the previous chunk is consumed
+        // one wave per staged row, lanes along it; loads from clamped (valid)
+        // addresses, then a select, so a wave's loads are in flight together
+        for (int row = threadIdx.x >> 6; row < nzc * R; row += kBlockF / 64) {
+            const int z = row / R, r = row % R;
+            const float* src =
+                d.m1 + (((size_t)(z0 + z) * d.kt + kt) * d.na_v + va0 + min(r, nr - 1)) * d.nx;
+            float* dst = ms + z * pitch + r;
+#pragma unroll 4
+            for (int ix = lane; ix < d.nx + W - 1; ix += 64) {
+                const float v = src[min(ix, d.nx - 1)];
+                dst[ix * R] = r < nr && ix < d.nx ? v : 0.0f;
+            }
+        }
+        __syncthreads();
+        if (!live) continue;
+        for (int z = 0; z < nzc; z += kGroup) {
+            float part[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) part[r] = 0.0f;
+#pragma unroll
+            for (int g = 0; g < kGroup; ++g) {
+                if (z + g >= nzc) break;
+                const int zs = so + (z0 + z + g) * sstep;
+                const int s0 = d.bs1.start[zs];
+                const int wo = zs + (zs - ua) * (W - 1);   // (table * W) * na_u + ua
+                const float* mz = ms + (z + g) * pitch + s0 * R;
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    const float wk = d.bs1.w[wo + k * d.na_u];
+                    float m[R];
+                    lds_rows<R>(mz + k * R, m);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) part[r] = fmaf(wk, m[r], part[r]);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] += (double)part[r];
+        }
+    }
+    if (!live) return;
+    const int c = c0 + j / d.na_u;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (r < nr)
+            d.fa[((size_t)c * d.na_v + va0 + r) * d.na_u + ua] =
+                (float)acc[r] * d.mask[(size_t)(va0 + r) * d.na_u + ua];
+}
+
+// M2[c][vd][ua] = sum_k bt2[kt_c][vd][k] FA[c][st + k][ua]
+__global__ __launch_bounds__(kBlock) void k_pl_minor2(PlenDev d)
+{
+    const size_t total = (size_t)d.cells * d.nv * d.na_u;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * kBlock) {
+        const int ua = (int)(i % d.na_u);
+        const size_t q = i / d.na_u;
+        const int vd = (int)(q % d.nv);
+        const int c = (int)(q / d.nv);
+        const float* col = d.fa + (size_t)c * d.na_v * d.na_u + ua;
+        d.m2[i] = (float)band_dot(d.bt2, (size_t)d.cell_kt[c], vd, col, d.na_u, d.na_v);
+    }
+}
+
+// y[vd][ud] = sum_c sum_k bs2[ks_c][ud][k] M2[c][vd][st + k]
+__global__ __launch_bounds__(kBlock) void k_pl_major2(PlenDev d, float* __restrict__ y)
+{
+    const size_t total = (size_t)d.nv * d.nu;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * kBlock) {
+        const int ud = (int)(i % d.nu);
+        const int vd = (int)(i / d.nu);
+        double acc = 0.0;
+        for (int c = 0; c < d.cells; ++c) {
+            const float* row = d.m2 + ((size_t)c * d.nv + vd) * d.na_u;
+            acc += band_dot(d.bs2, (size_t)d.cell_ks[c], ud, row, 1, d.na_u);
+        }
+        y[i] = (float)acc;
+    }
+}
+
+// M2[c][vd][ua] = sum_k bs2t[ks_c][ua][k] y[vd][st + k]
+__global__ __launch_bounds__(kBlock) void k_pl_major2_t(PlenDev d, const float* __restrict__ y)
+{
+    const size_t total = (size_t)d.cells * d.nv * d.na_u;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * kBlock) {
+        const int ua = (int)(i % d.na_u);
+        const size_t q = i / d.na_u;
+        const int vd = (int)(q % d.nv);
+        const int c = (int)(q / d.nv);
+        d.m2[i] = (float)band_dot(d.bs2t, (size_t)d.cell_ks[c], ua, y + (size_t)vd * d.nu, 1, d.nu);
+    }
+}
+
+// FA[c][va][ua] = mask[va][ua] * sum_k bt2t[kt_c][va][k] M2[c][st + k][ua]
+__global__ __launch_bounds__(kBlock) void k_pl_minor2_t(PlenDev d)
+{
+    const size_t total = (size_t)d.cells * d.na_v * d.na_u;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * kBlock) {
+        const int ua = (int)(i % d.na_u);
+        const size_t q = i / d.na_u;
+        const int va = (int)(q % d.na_v);
+        const int c = (int)(q / d.na_v);
+        const float* col = d.m2 + (size_t)c * d.nv * d.na_u + ua;
+        d.fa[i] = (float)band_dot(d.bt2t, (size_t)d.cell_kt[c], va, col, d.na_u, d.nv) *
+                  d.mask[(size_t)va * d.na_u + ua];
+    }
+}
+
+// M1[iz][kt][va][ix] = sum_{c in row kt} sum_k bs1t[iz, ks_c][ix][k] FA[c][va][st + k]
+__global__ __launch_bounds__(kBlock) void k_pl_major1_t(PlenDev d)
+{
+    const size_t total = (size_t)d.nz * d.kt * d.na_v * d.nx;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * kBlock) {
+        const int ix = (int)(i % d.nx);
+        size_t q = i / d.nx;
+        const int va = (int)(q % d.na_v);
+        q /= d.na_v;
+        const int kt = (int)(q % d.kt);
+        const int iz = (int)(q / d.kt);
+        double acc = 0.0;
+        for (int c = d.cell_first[kt]; c < d.cell_first[kt + 1]; ++c) {
+            const float* row = d.fa + ((size_t)c * d.na_v + va) * d.na_u;
+            acc += band_dot(d.bs1t, (size_t)iz * d.ks + d.cell_ks[c], ix, row, 1, d.na_u);
+        }
+        d.m1[i] = (float)acc;
+    }
+}
+
+// k_pl_major1_t with the loop bound W >= the table width fixed at compile
+// time (terms past the width are skipped).
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_pl_major1_t_w(PlenDev d)
+{
+    const size_t total = (size_t)d.nz * d.kt * d.na_v * d.nx;
+    const int wd = d.bs1t.width;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * kBlock) {
+        const int ix = (int)(i % d.nx);
+        size_t q = i / d.nx;
+        const int va = (int)(q % d.na_v);
+        q /= d.na_v;
+        const int kt = (int)(q % d.kt);
+        const int iz = (int)(q / d.kt);
+        double acc = 0.0;
+        for (int c = d.cell_first[kt]; c < d.cell_first[kt + 1]; ++c) {
+            const size_t tab = (size_t)iz * d.ks + d.cell_ks[c];
+            const int s0 = d.bs1t.start[tab * d.nx + ix];
+            const float* w = d.bs1t.w + tab * wd * (size_t)d.nx + ix;
+            const float* row = d.fa + ((size_t)c * d.na_v + va) * d.na_u;
+#pragma unroll
+            for (int k = 0; k < W; ++k)
+                if (k < wd) acc += (double)(w[(size_t)k * d.nx] * row[min(s0 + k, d.na_u - 1)]);
+        }
+        d.m1[i] = (float)acc;
+    }
+}
+
+// k_pl_major1_t with the array-plane rows staged in LDS: a workgroup takes
+// R array rows of one angular row kt (the rows of all its cells, staged once,
+// coalesced, the R rows of one array column adjacent so one LDS read serves
+// all R) and a chunk of slices; a thread takes one (slice, voxel column), loads each
+// cell's band weights once and applies them to the R staged rows.  Sums:
+// FP32 over one cell's band, FP64 across cells.  W >= the table's width
+// (terms past it skipped).
+constexpr int kBlockT = 1024;   // 16 waves share one staged row block
+
+template <int R, int W>
+__global__ __launch_bounds__(kBlockT) void k_pl_major1_t_lds(PlenDev d, int zchunk)
+{
+    extern __shared__ float4 fs4[];
+    float* fs = reinterpret_cast<float*>(fs4);             // [cell of the row][na_u][R]
+    const int nvb = (d.na_v + R - 1) / R;
+    const int kt = blockIdx.x / nvb;
+    const int va0 = (blockIdx.x % nvb) * R;
+    const int nr = min(R, d.na_v - va0);
+    const int c0 = d.cell_first[kt], nc = d.cell_first[kt + 1] - c0;
+    const int pitch = d.na_u * R;                          // floats per staged cell
+    // one wave per staged row, lanes along it; loads from valid rows, then a
+    // select, so a wave's loads are in flight together
+    const int lane = threadIdx.x & 63;
+    for (int row = threadIdx.x >> 6; row < nc * R; row += kBlockT / 64) {
+        const int c = row / R, r = row % R;
+        const float* src = d.fa + ((size_t)(c0 + c) * d.na_v + va0 + min(r, nr - 1)) * d.na_u;
+        float* dst = fs + c * pitch + r;
+#pragma unroll 4
+        for (int ua = lane; ua < d.na_u; ua += 64) {
+            const float v = src[ua];
+            dst[ua * R] = r < nr ? v : 0.0f;
+        }
+    }
+    __syncthreads();
+    const int iz0 = blockIdx.y * zchunk;
+    const int iz1 = min(d.nz, iz0 + zchunk);
+    const int wd = d.bs1t.width;
+    const int items = (iz1 - iz0) * d.nx;
+    for (int it = threadIdx.x; it < items; it += kBlockT) {
+        const int iz = iz0 + it / d.nx;
+        const int ix = it % d.nx;
+        double acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = 0.0;
+#pragma unroll 2
+        for (int c = 0; c < nc; ++c) {
+            // 32-bit table offsets (the launcher checks the tables' sizes)
+            const int tab = iz * d.ks + d.cell_ks[c0 + c];
+            const int s0 = d.bs1t.start[tab * d.nx + ix];
+            const int wo = tab * wd * d.nx + ix;
+            const float* fc = fs + c * pitch;
+            float part[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) part[r] = 0.0f;
+#pragma unroll
+            for (int k = 0; k < W; ++k)
+                if (k < wd) {
+                    const float wk = d.bs1t.w[wo + k * d.nx];
+                    float f[R];
+                    lds_rows<R>(fc + min(s0 + k, d.na_u - 1) * R, f);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) part[r] = fmaf(wk, f[r], part[r]);
+                }
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] += (double)part[r];
+        }
+        float* out = d.m1 + (((size_t)iz * d.kt + kt) * d.na_v + va0) * d.nx + ix;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (r < nr) out[(size_t)r * d.nx] = (float)acc[r];
+    }
+}
+
+template <int R>
+void launch_major1_t_lds(const PlenDev& p, int wb, int zchunk, dim3 g, hipStream_t s)
+{
+    const size_t lds = (size_t)std::max(1, p.row_cells_max) * R * p.na_u * sizeof(float);
+    if (wb == 8)
+        hipLaunchKernelGGL((k_pl_major1_t_lds<R, 8>), g, dim3(kBlockT), lds, s, p, zchunk);
+    else if (wb == 16)
+        hipLaunchKernelGGL((k_pl_major1_t_lds<R, 16>), g, dim3(kBlockT), lds, s, p, zchunk);
+    else
+        hipLaunchKernelGGL((k_pl_major1_t_lds<R, 24>), g, dim3(kBlockT), lds, s, p, zchunk);
+}
+
+// Stage-1 major pass of A: the LDS-staged kernel for table widths up to 4
+// while 4 rows of one slice fit 64 KiB, else the global-gather kernels.
+void launch_major1(const PlenDev& p, hipStream_t s)
+{
+    constexpr int R = 4;
+    const int w = std::max(1, p.bs1.width);
+    const int zc = 65536 / ((p.nx + w - 1) * R * (int)sizeof(float));    // slices per 64 KiB chunk
+    const int nvb = (p.na_v + R - 1) / R;
+    const int ncb = (int)(((size_t)p.row_cells_max * p.na_u + kBlockF - 1) / kBlockF);
+    const size_t nblocks = (size_t)p.kt * nvb * ncb;
+    const size_t lds = (size_t)std::max(1, zc) * (p.nx + w - 1) * R * sizeof(float);
+    const bool staged = zc >= 1 && nblocks < (1u << 31) && (size_t)p.row_cells_max * p.na_u < (1u << 31) &&
+                        (size_t)p.nz * p.ks * p.bs1.width * p.na_u < (1u << 31);
+    const dim3 gs((unsigned)nblocks), bf(kBlockF), b(kBlock);
+    const dim3 g1(grid_for((size_t)p.cells * p.na_v * p.na_u));
+    switch (staged ? p.bs1.width : -p.bs1.width) {
+    case 1: hipLaunchKernelGGL((k_pl_major1_lds<R, 1>), gs, bf, lds, s, p, zc, ncb); break;
+    case 2: hipLaunchKernelGGL((k_pl_major1_lds<R, 2>), gs, bf, lds, s, p, zc, ncb); break;
+    case 3: hipLaunchKernelGGL((k_pl_major1_lds<R, 3>), gs, bf, lds, s, p, zc, ncb); break;
+    case 4: hipLaunchKernelGGL((k_pl_major1_lds<R, 4>), gs, bf, lds, s, p, zc, ncb); break;
+    case -1: hipLaunchKernelGGL(k_pl_major1_w<1>, g1, b, 0, s, p); break;
+    case -2: hipLaunchKernelGGL(k_pl_major1_w<2>, g1, b, 0, s, p); break;
+    case -3: hipLaunchKernelGGL(k_pl_major1_w<3>, g1, b, 0, s, p); break;
+    case -4: hipLaunchKernelGGL(k_pl_major1_w<4>, g1, b, 0, s, p); break;
+    default: hipLaunchKernelGGL(k_pl_major1, g1, b, 0, s, p); break;
+    }
+}
+
+// Stage-1 major pass of A^T: the LDS-staged kernel while R >= 1 rows of every
+// cell of one angular row fit 64 KiB, else the global-gather kernels.
+void launch_major1_t(const PlenDev& p, hipStream_t s)
+{
+    const int wb = p.bs1t.width <= 8 ? 8 : p.bs1t.width <= 16 ? 16 : 24;
+    int R = 8;
+    while (R >= 1 && (size_t)p.row_cells_max * R * p.na_u * sizeof(float) > 65536) R /= 2;
+    if (R >= 1 && p.bs1t.width <= 24 && (size_t)p.nz * p.ks * p.bs1t.width * p.nx < (1u << 31)) {
+        const int nvb = (p.na_v + R - 1) / R;
+        const int zsplit = std::max(1, std::min(p.nz, (1024 + p.kt * nvb - 1) / (p.kt * nvb)));
+        const int zchunk = (p.nz + zsplit - 1) / zsplit;
+        const dim3 g((unsigned)(p.kt * nvb), (unsigned)((p.nz + zchunk - 1) / zchunk));
+        switch (R) {
+        case 8: launch_major1_t_lds<8>(p, wb, zchunk, g, s); return;
+        case 4: launch_major1_t_lds<4>(p, wb, zchunk, g, s); return;
+        case 2: launch_major1_t_lds<2>(p, wb, zchunk, g, s); return;
+        default: launch_major1_t_lds<1>(p, wb, zchunk, g, s); return;
+        }
+    }
+    const dim3 g1(grid_for((size_t)p.nz * p.kt * p.na_v * p.nx)), b(kBlock);
+    if (p.bs1t.width <= 8)
+        hipLaunchKernelGGL(k_pl_major1_t_w<8>, g1, b, 0, s, p);
+    else if (p.bs1t.width <= 16)
+        hipLaunchKernelGGL(k_pl_major1_t_w<16>, g1, b, 0, s, p);
+    else if (p.bs1t.width <= 24)
+        hipLaunchKernelGGL(k_pl_major1_t_w<24>, g1, b, 0, s, p);
+    else
+        hipLaunchKernelGGL(k_pl_major1_t, g1, b, 0, s, p);
+}
+
+}  // namespace
+
+hipError_t launch_plen_project(const PlenDev& p, const float* x, float* y, hipStream_t s)
+{
+    // stage 1 minor pass: the transport's t filter onto the array plane
+    XportDev d{};
+    d.nx = p.nx; d.ny = p.ny; d.nz = p.nz; d.nu = p.na_u; d.nv = p.na_v; d.kt = p.kt;
+    d.bt = p.bt1;
+    d.mid = p.m1;
+    const size_t nm = (size_t)p.nz * p.kt * p.na_v * p.nx;
+    hipLaunchKernelGGL(k_minor_fwd, dim3(grid_for(nm)), dim3(kBlock), 0, s, d, x);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    launch_major1(p, s);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pl_minor2, dim3(grid_for((size_t)p.cells * p.nv * p.na_u)), dim3(kBlock), 0, s, p);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pl_major2, dim3(grid_for((size_t)p.nv * p.nu)), dim3(kBlock), 0, s, p, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_plen_backproject(const PlenDev& p, const float* y, float* x, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pl_major2_t, dim3(grid_for((size_t)p.cells * p.nv * p.na_u)), dim3(kBlock), 0, s, p, y);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pl_minor2_t, dim3(grid_for((size_t)p.cells * p.na_v * p.na_u)), dim3(kBlock), 0, s, p);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    launch_major1_t(p, s);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // stage 1 minor pass transposed: sums the angular rows per voxel
+    XportDev d{};
+    d.nx = p.nx; d.ny = p.ny; d.nz = p.nz; d.nu = p.na_u; d.nv = p.na_v; d.kt = p.kt;
+    d.btt = p.bt1t;
+    d.mid = p.m1;
+    hipLaunchKernelGGL(k_minor_adj, dim3(grid_for((size_t)p.nz * p.ny * p.nx)), dim3(kBlock), 0, s, d, x);
     return hipGetLastError();
 }
 

@@ -165,8 +165,20 @@ def test_transport_operator_validation(L):
         assert L.lib().ltm_xport_create(ctypes.byref(L.make_grid(g)), L.make_cameras([cam]), 1,
                                         ctypes.byref(h)) == 0
         L.lib().ltm_xport_destroy(h)
+    # head-on square-array plenoptic: the factorized model, three intermediates
+    pl = W.plenoptic_camera(64, 4, (3, 3), 8)
+    assert L.lib().ltm_xport_create(ctypes.byref(L.make_grid(g)), L.make_cameras([pl]), 1,
+                                    ctypes.byref(h)) == 0
+    n = ctypes.c_uint64()
+    assert L.lib().ltm_xport_workspace_bytes(h, ctypes.byref(n)) == 0
+    cells = 9                                            # 3 x 3 cells, all centres inside the disc
+    assert n.value >= 4 * (24 * 3 * 64 * 24 + 2 * cells * 64 * 64)
+    b = (ctypes.c_uint32 * 4)()
+    assert L.lib().ltm_xport_bands(h, b) == 0 and all(v >= 1 for v in b)
+    L.lib().ltm_xport_destroy(h)
     cases = [(W.single_lens_camera(128, (4, 4), 8, phi_deg=50.0), L.LTM_ERR_UNSUPPORTED, "45 deg"),
-             (W.plenoptic_camera(64, 4, (2, 2), 8), L.LTM_ERR_UNSUPPORTED, "single-lens"),
+             (W.plenoptic_camera(64, 4, (2, 2), 8, phi_deg=20.0), L.LTM_ERR_UNSUPPORTED, "head-on"),
+             (W.hex_plenoptic_camera(64, (4, 4)), L.LTM_ERR_UNSUPPORTED, "square-array"),
              (W.single_lens_camera(128, (4, 4), 8, distance=10.0), L.LTM_ERR_INVALID, "in front")]
     for cam, status, needle in cases:
         st = L.lib().ltm_xport_create(ctypes.byref(L.make_grid(g)), L.make_cameras([cam]), 1,

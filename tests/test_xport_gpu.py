@@ -1,12 +1,14 @@
 """GPU parity of the paper's own discretization (L2-projected light-field
-transport, Dirac and pillbox angular bases, head-on single-lens camera)
+transport, Dirac and pillbox angular bases; single-lens cameras, head-on
+and posed, and the factorized model of a square-array plenoptic camera)
 against the FP64 oracle of ``oracle/transport.py``, which builds every
 transport factor as a dense matrix from the tables.  Bars: relative L2
 <= 1e-5 for A x and A^T y (FP32 table entries and intermediate, FP64
 accumulation), the dot identity to 1e-9 at workload sizes (1e-8 on the
-small grids of the posed cases: a posed camera stores three FP32
-intermediates per direction -- the two sheared volumes and the filtering
-intermediate -- whose independent roundings stay visible with few effective
+small grids of the posed cases, 3e-8 on those of the plenoptic model: a
+posed camera stores three FP32 intermediates per direction -- the two
+sheared volumes and the filtering intermediate -- and the plenoptic model
+three others, whose independent roundings stay visible with few effective
 terms), and the GPU A built column by column equal to the GPU A^T entry by
 entry."""
 import numpy as np
@@ -150,3 +152,98 @@ def test_posed_transport_paper_size_vs_ray_model(ltm):
     assert dot < 1e-9
     assert abs(Ax.sum() / Ar.sum() - 1.0) < 2e-3
     assert d < 0.1
+
+
+# ------------------------------------------------- factorized plenoptic model
+def _plen_dot(Ax, y, x, Aty):
+    x64, y64 = np.asarray(x, np.float64).reshape(-1), np.asarray(y, np.float64).reshape(-1)
+    return abs(Ax.astype(np.float64) @ y64 - x64 @ Aty.astype(np.float64)) / (
+        np.linalg.norm(Ax) * np.linalg.norm(y64))
+
+
+@pytest.mark.parametrize("basis", [0, 1])
+@pytest.mark.parametrize("dims,pitch,det,mla,rays,r_main", [((16, 16, 16), 6.0, 64, 8, (8, 8), 3.0),
+                                                            ((20, 14, 10), 4.0, 96, 8, (4, 6), None),
+                                                            ((12, 12, 9), 8.0, 128, 16, (5, 5), None),
+                                                            # wide stage-1 bands: the kernels
+                                                            # without LDS staging
+                                                            ((24, 20, 6), 0.1, 64, 8, (2, 2), None),
+                                                            ((10, 10, 7), 12.0, 128, 16, (3, 3), None)])
+def test_plenoptic_transport_matches_oracle(ltm, basis, dims, pitch, det, mla, rays, r_main):
+    g = W.grid(dims, pitch)
+    cam = W.plenoptic_camera(det, mla, rays, 8)
+    if r_main is not None:
+        cam["r_main"] = r_main
+    x = W.flame(max(dims), seed=5)[:dims[2], :dims[1], :dims[0]]
+    y = W.uniform_random(det * det, seed=6)
+    op = ltm.Transport(g, cam, basis)
+    Ax = op.project(_dev(x)).cpu().numpy()
+    Aty = op.backproject(_dev(y)).cpu().numpy()
+    ref_Ax = OT.project_plenoptic(g, cam, x, basis)
+    ref_Aty = OT.backproject_plenoptic(g, cam, y, basis)
+    e1, e2 = rel_l2(Ax, ref_Ax), rel_l2(Aty, ref_Aty)
+    dot = _plen_dot(Ax, y, x, Aty)
+    print(f"plenoptic transport basis={basis} dims={dims} det={det}/{mla} K={rays}: A {e1:.2e} "
+          f"A^T {e2:.2e} dot {dot:.2e} bands {op.bands()}", flush=True)
+    assert np.linalg.norm(ref_Ax) > 0 and np.linalg.norm(ref_Aty) > 0
+    assert e1 < 1e-5 and e2 < 1e-5
+    # three FP32 intermediates per direction (slices filtered along t, the
+    # masked array-plane light field, the lenslet t stage) round
+    # independently; with a few thousand pixels their noise stays visible
+    # (measured up to 1.2e-8); at 48^3 x 256^2 and beyond it is below 1e-9
+    assert dot < 3e-8
+
+
+def test_plenoptic_transport_entrywise_transpose(ltm):
+    g = W.grid((4, 5, 3), 8.0)
+    cam = W.plenoptic_camera(16, 4, (2, 2), 8)
+    op = ltm.Transport(g, cam, 1)
+    N, M = 60, 256
+    A = np.zeros((M, N))
+    for j in range(N):
+        e = torch.zeros(N, device="cuda")
+        e[j] = 1.0
+        A[:, j] = op.project(e).cpu().numpy()
+    AT = np.zeros((N, M))
+    for i in range(M):
+        e = torch.zeros(M, device="cuda")
+        e[i] = 1.0
+        AT[:, i] = op.backproject(e).cpu().numpy()
+    assert np.count_nonzero(A) > 0.02 * A.size
+    # the same FP32 entries both ways; sums of up to a few FP32 products
+    # rounded once to FP32 per stage
+    assert np.max(np.abs(A - AT.T)) <= 1e-6 * np.max(np.abs(A))
+
+
+def test_plenoptic_transport_mid_size_matches_oracle(ltm):
+    # 48^3 voxels, 256^2 pixels behind 16^2 lenslets, 4 x 4 cells
+    g = W.grid(48, 2.5)
+    cam = W.plenoptic_camera(256, 16, (4, 4), 8)
+    x = W.flame(48, seed=7)
+    y = W.uniform_random(256 * 256, seed=8)
+    op = ltm.Transport(g, cam, 1)
+    Ax = op.project(_dev(x)).cpu().numpy()
+    Aty = op.backproject(_dev(y)).cpu().numpy()
+    e1 = rel_l2(Ax, OT.project_plenoptic(g, cam, x, 1))
+    e2 = rel_l2(Aty, OT.backproject_plenoptic(g, cam, y, 1))
+    dot = _plen_dot(Ax, y, x, Aty)
+    print(f"plenoptic transport 48^3 x 256^2: A {e1:.2e} A^T {e2:.2e} dot {dot:.2e}", flush=True)
+    # the FP32 image alone contributes about 2^-24 / sqrt(N_eff) with some 3e4
+    # lit pixels (4e-10), and each of the three FP32 intermediates as much
+    # again: measured 3e-10 .. 1.3e-9 as the kernels' rounding changed
+    assert e1 < 1e-5 and e2 < 1e-5 and dot < 3e-9
+
+
+def test_plenoptic_transport_full_size_dot(ltm):
+    # 128^3 voxels at 1.25 mm, 1024^2 pixels behind 64^2 lenslets, 4 x 4 cells
+    g = W.grid(128, 1.25)
+    cam = W.plenoptic_camera(1024, 64, (4, 4), 8)
+    op = ltm.Transport(g, cam, 1)
+    x = torch.from_numpy(W.flame(128, seed=9).reshape(-1)).cuda()
+    y = torch.from_numpy(W.uniform_random(1024 * 1024, seed=10)).cuda()
+    Ax = op.project(x).double()
+    Aty = op.backproject(y).double()
+    dot = abs(float(Ax @ y.double()) - float(x.double() @ Aty)) / (
+        float(Ax.norm()) * float(y.double().norm()))
+    print(f"plenoptic transport 128^3 x 1024^2: dot {dot:.2e} |Ax| {float(Ax.norm()):.3e}", flush=True)
+    assert float(Ax.norm()) > 0 and dot < 1e-9
