@@ -288,6 +288,9 @@ ltm_status create_plenoptic(const ltm_grid* g, const ltm_camera* c, uint32_t bas
     const int nx = (int)g->nx, ny = (int)g->ny, nz = (int)g->nz;
     const int nu = (int)c->det_nu, nv = (int)c->det_nv, mu = (int)c->mla_nu, mv = (int)c->mla_nv;
     const int ka = nu / mu;
+    if (nv / mv != ka)
+        return fail(LTM_ERR_UNSUPPORTED, "the factorized plenoptic transport needs square lenslets "
+                                         "(det_nu / mla_nu == det_nv / mla_nv)");
     const int Ks = (int)c->rays_u, Kt = (int)c->rays_v;
     const double dx = g->pitch_mm, dp = c->pixel_pitch_mm, P = ka * dp, da = dp;
     const double r = c->r_main_mm, d0s = 2.0 * r / Ks, d0t = 2.0 * r / Kt;

@@ -179,6 +179,8 @@ def test_transport_operator_validation(L):
     cases = [(W.single_lens_camera(128, (4, 4), 8, phi_deg=50.0), L.LTM_ERR_UNSUPPORTED, "45 deg"),
              (W.plenoptic_camera(64, 4, (2, 2), 8, phi_deg=20.0), L.LTM_ERR_UNSUPPORTED, "head-on"),
              (W.hex_plenoptic_camera(64, (4, 4)), L.LTM_ERR_UNSUPPORTED, "square-array"),
+             (dict(W.plenoptic_camera(64, 4, (2, 2), 8), det_nv=32), L.LTM_ERR_UNSUPPORTED,
+              "square lenslets"),
              (W.single_lens_camera(128, (4, 4), 8, distance=10.0), L.LTM_ERR_INVALID, "in front")]
     for cam, status, needle in cases:
         st = L.lib().ltm_xport_create(ctypes.byref(L.make_grid(g)), L.make_cameras([cam]), 1,
