@@ -118,7 +118,9 @@ typedef struct ltm_camera {
  * different samples; bit 2 (adjoint) accumulates the brick in FP32 before the
  * FP64 flush; bit 3 (adjoint) staggers the lanes' walks along their rays;
  * bit 4 (adjoint) merges consecutive samples of one trilinear cell in
- * registers before the LDS atomics.  Each workgroup
+ * registers before the LDS atomics; bit 5 (adjoint) instead keeps two planes
+ * of corner sums across the ray's dominant axis, so a step along that axis
+ * flushes 4 corners, not 8.  Each workgroup
  * marches its rays through consecutive slabs of chunk_mm camera depth,
  * staging the voxels the slab's rays touch in an LDS brick of at most
  * brick_floats floats (a slab whose brick does not fit uses global memory).

@@ -63,8 +63,9 @@ def candidates(plan, cam_index: int, direction: int):
                     splits = max(1, items // per)
                     if items % splits or items // splits > 2048 or items // splits * R > 8192:
                         continue
-                    # bit 3 staggers sample walks, bit 4 merges a cell's samples
-                    for order in (3, 24, 26, 27):
+                    # bit 3 staggers sample walks, bit 4 merges a cell's samples,
+                    # bit 5 keeps two-plane windows along the dominant axis
+                    for order in (3, 26, 27, 42, 43):
                         for chunk in (16, 32):
                             for brick in (8192, 12288):
                                 out.append(dict(tile_u=t, tile_v=t, block_u=blk, block_v=blk,

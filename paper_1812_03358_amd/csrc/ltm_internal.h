@@ -74,6 +74,7 @@ struct CamDev {
     int adj_f32;          // adjoint: FP32 LDS brick (flushed into the FP64 accumulator)
     int skew;             // adjoint: lanes start their sample walk at staggered offsets
     int merge;            // adjoint: merge consecutive samples of one cell in registers
+    int window;           // adjoint: two planes of corner sums along the ray's dominant axis
     int sub_n, sub_i;     // angular-sample subset: keep r with r mod sub_n == sub_i
     int items, items_per_split, tiles_u, tiles_v, n_tiles;
     int brick_cap;        // LDS brick capacity in voxels (FP32 forward, FP64 adjoint)

@@ -144,7 +144,7 @@ ltm_status check_tiling(const ltm_camera& c, const ltm_tiling& t)
         return fail(LTM_ERR_INVALID, "tiling sizes must be positive");
     if (c.kind != LTM_PLENOPTIC && (t.block_u == 0 || t.block_v == 0))
         return fail(LTM_ERR_INVALID, "single-lens and hexagonal tilings need block sizes");
-    if (t.order > 31) return fail(LTM_ERR_INVALID, "tiling order flags must be 0..31");
+    if (t.order > 63) return fail(LTM_ERR_INVALID, "tiling order flags must be 0..63");
     if (t.brick_floats > (uint32_t)kMaxBrickFloats)
         return fail(LTM_ERR_INVALID, "brick larger than 64 KiB of LDS");
     if (!(t.chunk_mm > 0) || !std::isfinite(t.chunk_mm))
@@ -172,8 +172,10 @@ ltm_tiling default_tiling(const ltm_grid& g, const ltm_camera& c, int dir)
     //  * forward: lanes of one lenslet / pixel block on adjacent lanes read
     //    the same LDS words (a bundle is a fraction of a voxel wide); no
     //    rotation of the starting angular sample; ~1-4k rays per group;
-    //  * adjoint: staggered sample walks and merged cells (bits 3, 4) break
-    //    the LDS atomic collisions of converging bundles; with many rays per
+    //  * adjoint: staggered sample walks and two-plane windows along the
+    //    rays' dominant axis (bits 3, 5) break the LDS atomic collisions of
+    //    converging bundles and halve the atomics per cell step (4-14%
+    //    faster than merged cells, bit 4, on the benchmark workloads); with many rays per
     //    pixel, lanes also walk across lenslets / blocks (bit 0) and the slabs
     //    get thinner.  The square-array plenoptic camera with R <= 4 keeps
     //    4x4 lenslets and 256 pixels per group (fastest on the 128^3 case).
@@ -194,13 +196,13 @@ ltm_tiling default_tiling(const ltm_grid& g, const ltm_camera& c, int dir)
         while (t.splits < items && items / t.splits * R > target) t.splits *= 2;
     } else if (pl && R <= 4) {
         t.tile_u = t.tile_v = 4;
-        t.order = 2 | 8 | 16;
+        t.order = 2 | 8 | 32;
         t.chunk_mm = 32.0 * g.pitch_mm;
         t.splits = (uint32_t)std::max<uint64_t>(1, 16 * k / 256);   // 256 pixels per group
     } else {
         t.tile_u = t.tile_v = 2;
         t.block_u = t.block_v = 8;
-        t.order = (c.kind == LTM_PLENOPTIC_HEX ? 0 : 1) | 2 | 8 | 16;
+        t.order = (c.kind == LTM_PLENOPTIC_HEX ? 0 : 1) | 2 | 8 | 32;
         t.chunk_mm = (c.kind == LTM_PLENOPTIC_HEX ? 32.0 : 16.0) * g.pitch_mm;
         const uint64_t items = 4 * (pl ? k : 64);
         t.splits = 1;
@@ -317,6 +319,7 @@ void apply_tiling(const ltm_grid& g, const ltm_camera& c, const ltm_tiling& t, C
     d.adj_f32 = (t.order & 4) ? 1 : 0;
     d.skew = (t.order & 8) ? 1 : 0;
     d.merge = (t.order & 16) ? 1 : 0;
+    d.window = (t.order & 32) ? 1 : 0;
     d.splits = (int)t.splits;
     d.items = d.tile_u * d.tile_v * d.ku * d.kv;
     d.items_per_split = (d.items + d.splits - 1) / d.splits;

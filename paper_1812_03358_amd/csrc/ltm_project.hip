@@ -521,6 +521,81 @@ __device__ __forceinline__ void scatter_lds_merged(const March& mr, int m0, int 
     if (cur >= 0) flush(cur);
 }
 
+// As scatter_lds_merged, but a lane keeps two planes of corner sums across
+// the ray's dominant axis c (the 2 x 2 corners in the other two axes, at the
+// cell's low and high c): when a sample moves one cell along c, only the
+// plane left behind is flushed (4 atomics) and the other becomes the new
+// cell's low (or high) plane; any other move flushes both planes.  Rays
+// advance about half a voxel per sample, mostly along c, so most cell
+// changes flush 4 corners instead of 8.
+template <typename T>
+__device__ __forceinline__ void scatter_lds_window(const March& mr, int m0, int m1, const BrickRec& b,
+                                                   T* brick, float v, bool skew)
+{
+    const int sx = b.dim[0], sxy = b.dim[0] * b.dim[1];
+    const float maxi = (float)(b.dim[0] * b.dim[1] * b.dim[2] - 1 - (1 + sx + sxy));
+    // dominant axis c and the other two (a, b), per lane, by selects so that
+    // nothing leaves registers: c = x -> (a, b) = (y, z); c = y -> (x, z);
+    // c = z -> (x, y)
+    const float ax = fabsf(mr.st[0]), ay = fabsf(mr.st[1]), az = fabsf(mr.st[2]);
+    const int c = (az >= ax && az >= ay) ? 2 : (ay >= ax ? 1 : 0);
+    const int sa = c == 0 ? sx : 1, sb = c == 2 ? sx : sxy, sc = c == 0 ? 1 : (c == 1 ? sx : sxy);
+    const float qa0 = c == 0 ? mr.qs[1] : mr.qs[0], da = c == 0 ? mr.st[1] : mr.st[0];
+    const float qb0 = c == 2 ? mr.qs[1] : mr.qs[2], db = c == 2 ? mr.st[1] : mr.st[2];
+    const float qc0 = c == 0 ? mr.qs[0] : (c == 1 ? mr.qs[1] : mr.qs[2]);
+    const float dc = c == 0 ? mr.st[0] : (c == 1 ? mr.st[1] : mr.st[2]);
+    const float fsa = (float)sa, fsb = (float)sb, fsc = (float)sc;
+    const int cnt = m1 - m0;
+    int m = m0;
+    if (skew) m += (int)(((threadIdx.x & 63) * (unsigned)cnt) >> 6);
+    int cur = -1;
+    float lo[4] = {0.f, 0.f, 0.f, 0.f}, hi[4] = {0.f, 0.f, 0.f, 0.f};
+    auto flush4 = [&](int i, const float (&p)[4]) {
+        T* q = brick + i;
+        atomicAdd(q, (T)p[0]);
+        atomicAdd(q + sa, (T)p[1]);
+        atomicAdd(q + sb, (T)p[2]);
+        atomicAdd(q + sa + sb, (T)p[3]);
+    };
+    for (int k = 0; k < cnt; ++k) {
+        const float fm = (float)m;
+        const float qa = fmaf(fm, da, qa0), qb = fmaf(fm, db, qb0), qc = fmaf(fm, dc, qc0);
+        const float ca = floorf(qa), cb = floorf(qb), cc = floorf(qc);
+        const float fa = qa - ca, fb = qb - cb, fc = qc - cc;
+        // the cell's LDS index: exact integer arithmetic in FP32 (brick indices < 2^24)
+        const float fi = fmaf(cc, fsc, fmaf(cb, fsb, ca * fsa)) - b.base;
+        const int i0 = (int)clampf(fi, 0.0f, maxi);
+        if (i0 != cur) {
+            const bool up = i0 == cur + sc, down = i0 == cur - sc;
+            if (cur >= 0) {
+                if (!down) flush4(cur, lo);
+                if (!up) flush4(cur + sc, hi);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float l = lo[j];
+                lo[j] = up ? hi[j] : 0.0f;
+                hi[j] = down ? l : 0.0f;
+            }
+            cur = i0;
+        }
+        const float ga = 1.0f - fa, gb = 1.0f - fb;
+        const float vl = v * (1.0f - fc), vh = v * fc;
+        const float w[4] = {ga * gb, fa * gb, ga * fb, fa * fb};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            lo[j] = fmaf(vl, w[j], lo[j]);
+            hi[j] = fmaf(vh, w[j], hi[j]);
+        }
+        ++m;
+        m = m == m1 ? m0 : m;
+    }
+    if (cur >= 0) {
+        flush4(cur, lo);
+        flush4(cur + sc, hi);
+    }
+}
+
 __device__ __forceinline__ void scatter_global(const March& mr, int m0, int m1, const int n[3],
                                                double* __restrict__ x, const Bounds& bd, float v)
 {
@@ -660,6 +735,10 @@ __device__ void march_tile(const CamDev& c, int tile, const float* __restrict__ 
                 const float v = (float)m.item[item] * r.w;
                 if (!b.lds)
                     scatter_global(mr, m0, m1, c.n, xacc, bd, v);
+                else if (c.window && c.adj_f32)
+                    scatter_lds_window(mr, m0, m1, b, reinterpret_cast<float*>(m.brick), v, c.skew);
+                else if (c.window)
+                    scatter_lds_window(mr, m0, m1, b, reinterpret_cast<double*>(m.brick), v, c.skew);
                 else if (c.merge && c.adj_f32)
                     scatter_lds_merged(mr, m0, m1, b, reinterpret_cast<float*>(m.brick), bd, v, c.skew);
                 else if (c.merge)

@@ -111,6 +111,9 @@ def test_tilings_agree(orc, ltm):
         {"brick_floats": 0},
         {"tile_u": 2, "tile_v": 3, "order": 1, "splits": 3, "chunk_mm": 17.0},
         {"tile_u": 3, "tile_v": 1, "order": 0, "splits": 2, "brick_floats": 512, "chunk_mm": 400.0},
+        # adjoint plane windows along the rays' dominant axis, FP64 and FP32 bricks
+        {"order": 2 | 8 | 32},
+        {"order": 1 | 4 | 32, "chunk_mm": 30.0},
     ]
     for v in variants:
         Ax, Aty, _ = _run(ltm, g, cams, x, y, [(0, 0, v), (1, 0, v)])
@@ -127,6 +130,30 @@ def test_camera_behind_volume_sees_nothing(ltm):
     x = np.ones(512, np.float32)
     Ax, Aty, _ = _run(ltm, g, [cam], x, np.ones(256, np.float32))
     assert np.all(Ax == 0) and np.all(Aty == 0)
+
+
+@pytest.mark.parametrize("which", ["plenoptic_128", "differentiable_256"])
+def test_window_scatter_matches_merged(ltm, which):
+    # the plane-window adjoint (tiling bit 5) against the merged one (bit 4,
+    # checked against the oracle elsewhere) at full size: the same samples and
+    # weights, summed in another order
+    cfg = W.config_plenoptic() if which == "plenoptic_128" else W.config_differentiable()
+    g, cams = cfg["grid"], cfg["cameras"]
+    plan = ltm.Plan(g, cams)
+    y = torch.from_numpy(W.uniform_random(plan.n_meas, seed=36)).cuda()
+    for ci in range(len(cams)):
+        t = plan.get_tiling(1, ci).as_dict()
+        t["order"] = (t["order"] & ~32) | 16
+        plan.set_tiling(1, ci, t)
+    merged = plan.backproject(y).double()
+    for ci in range(len(cams)):
+        t = plan.get_tiling(1, ci).as_dict()
+        t["order"] = (t["order"] & ~16) | 32
+        plan.set_tiling(1, ci, t)
+    window = plan.backproject(y).double()
+    err = float(torch.linalg.norm(window - merged) / torch.linalg.norm(merged))
+    print(f"window vs merged {which}: {err:.2e}", flush=True)
+    assert err < 1e-6
 
 
 @pytest.mark.parametrize("kind", ["thin", "plen"])
