@@ -523,6 +523,99 @@ def run_plenoptic_transport(args):
     return out
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0   # dense BF16 MFMA, MI355X
+
+
+def run_warm_start_net(args):
+    """The warm-start network at 128^3 (one channel in, 16/32/64/128
+    channels): each 3x3x3 convolution's forward kernel timed with HIP events
+    on the stream it runs on, FLOPs = 2 x output voxels x cout x 27 x cin
+    (BF16 MFMA, FP32 accumulation); then one whole training step (forward,
+    MSE, backward, Adam, weight packing).  Inputs are random, weights He
+    initialized."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    from paper_1812_03358_amd import ltm, nn
+
+    n = 128
+    net = nn.UNet(seed=0)
+    x = torch.from_numpy(np.random.default_rng(0).uniform(0, 1, n ** 3).astype(np.float32)).cuda()
+    xin = net.prep_input(x)
+    target = torch.from_numpy(np.random.default_rng(1).uniform(0, 1, n ** 3).astype(np.float32)).cuda()
+    for _ in range(args.warmup):
+        net.forward(xin, n, n, n)
+    torch.cuda.synchronize()
+    # per-layer forward convolutions, each input as the full forward leaves it
+    A = net.acts
+    lib = ltm.lib()
+    rows, tot_flop, tot_ms = [], 0.0, 0.0
+    for name in nn.ORDER:
+        if name.startswith("p"):
+            continue
+        L = net.layers[name]
+        d, h, w = net._dims(name, n, n, n)
+        last = name == "out"
+        out = torch.empty(d * h * w * L.cout, dtype=torch.float32 if last else torch.int16, device="cuda")
+        desc = nn.conv_desc(L.ks, d, h, w, L.c0, L.c1, L.cout, L.up, 1, int(last))
+        in1 = A[L.ins[1]] if len(L.ins) > 1 else None
+        call = lambda: ltm._check(lib.ltm_nn_conv3d_forward(
+            ctypes.byref(desc), ctypes.c_void_p(A[L.ins[0]].data_ptr()),
+            ctypes.c_void_p(in1.data_ptr() if in1 is not None else 0), ctypes.c_void_p(L.wf.data_ptr()),
+            ctypes.c_void_p(L.b.data_ptr()), ctypes.c_void_p(out.data_ptr()), None, ltm._stream(None)))
+        call()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            call()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        flop = 2.0 * d * h * w * L.cout * L.ks ** 3 * L.cin
+        tot_flop += flop
+        tot_ms += ms
+        rows.append({"layer": name, "dhw": d, "cin": L.cin, "cout": L.cout, "ms": round(ms, 4),
+                     "tflops": round(flop / (ms * 1e-3) / 1e12, 1)})
+    # one training step
+    for _ in range(2):
+        net.zero_grad()
+        net.forward(xin, n, n, n)
+        _, g = net.loss_and_grad(target)
+        net.backward(g)
+        net.step(lr=1e-4)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        net.zero_grad()
+        net.forward(xin, n, n, n)
+        _, g = net.loss_and_grad(target)
+        net.backward(g)
+        net.step(lr=1e-4)
+    e1.record()
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / args.steps
+    dom = max(rows, key=lambda r: r["ms"])
+    dom_flop = 2.0 * (dom["dhw"] ** 3) * dom["cout"] * 27 * dom["cin"]
+    out = base_record(args, tot_flop / (tot_ms * 1e-3) / 1e12, tot_ms,
+                      "warm_start_net_128: the warm-start network's 3x3x3 BF16 convolutions at 128^3 "
+                      "(forward kernels of one network pass, each timed alone), then one training step",
+                      {"layers": rows})
+    out["metric"] = "warm-start network forward convolutions, TFLOP/s"
+    out["unit"] = "TFLOP/s"
+    out["dtype"] = "bf16"
+    ach = dom_flop / (dom["ms"] * 1e-3) / 1e12
+    out["roofline"] = {"bound": "mfma", "achieved": round(ach, 1), "peak": MFMA_BF16_PEAK_TFLOPS,
+                       "unit": "TFLOP/s", "frac": round(ach / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None,
+                       "kernel": f"conv3d forward, layer {dom['layer']}"}
+    out["ms_forward_convs"] = round(tot_ms, 4)
+    out["ms_train_step"] = round(step_ms, 4)
+    return out
+
+
 def run_warm_start(args):
     """Learned warm start (2 plenoptic cameras at 0/90 deg, 128^3): train the
     network on projector-generated pairs for a time budget, then time the
@@ -571,7 +664,7 @@ def main():
                     choices=["plenoptic_128", "thin_lens_32", "differentiable_256", "batched_48",
                              "recon_plenoptic_128", "recon_three_camera_100", "warm_start_128",
                              "hex_plenoptic_100", "transport_100",
-                             "plenoptic_transport_128"])
+                             "plenoptic_transport_128", "warm_start_net_128"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", action="store_true")
@@ -612,6 +705,8 @@ def main():
         out = run_transport(args)
     elif args.workload == "plenoptic_transport_128":
         out = run_plenoptic_transport(args)
+    elif args.workload == "warm_start_net_128":
+        out = run_warm_start_net(args)
     elif args.workload == "batched_48":
         out = run_batched(args)
     elif args.workload == "warm_start_128":

@@ -10,6 +10,8 @@
 // Operand lane layout of the 16x16x32 instruction: lane l supplies
 // A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16], j = 0..7, and
 // holds D[4 (l / 16) + i][l % 16], i = 0..3.
+#include <algorithm>
+
 #include "ltm_internal.h"
 #include "ltm_nn.h"
 
@@ -289,6 +291,33 @@ __global__ void k_sumpool(const float* __restrict__ dh, float* __restrict__ dl, 
 }
 
 // g = dOut * (out > 0) as BF16 (the MFMA operand) and its per-channel sum.
+// When C divides the grid stride (C a power of two up to 256) every thread
+// keeps one channel: its sum stays in a register, lanes of one channel are
+// combined with wave shuffles and each wave adds C values into LDS.
+__global__ void k_relu_mask_pc(const float* __restrict__ dout, const u16* __restrict__ out, int relu,
+                               u16* __restrict__ g, float* __restrict__ dbias, size_t n, int C)
+{
+    extern __shared__ float sb[];
+    for (int c = threadIdx.x; c < C; c += blockDim.x) sb[c] = 0.0f;
+    __syncthreads();
+    float part = 0.0f;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        float v = dout[i];
+        if (relu && !(bf2f(out[i]) > 0.0f)) v = 0.0f;
+        const u16 b = f2bf(v);
+        g[i] = b;
+        part += bf2f(b);
+    }
+    // lanes l and l + C (C < 64) hold the same channel
+    for (int o = 32; o >= C && o > 0; o >>= 1) part += __shfl_xor(part, o);
+    const int lane = threadIdx.x & 63;
+    if (lane < C && part != 0.0f) atomicAdd(&sb[threadIdx.x % C], part);
+    __syncthreads();
+    if (dbias)
+        for (int c = threadIdx.x; c < C; c += blockDim.x)
+            if (sb[c] != 0.0f) unsafeAtomicAdd(&dbias[c], sb[c]);
+}
+
 __global__ void k_relu_mask(const float* __restrict__ dout, const u16* __restrict__ out, int relu,
                             u16* __restrict__ g, float* __restrict__ dbias, size_t n, int C)
 {
@@ -460,14 +489,20 @@ hipError_t nn_sumpool(const float* dh, float* dl, int D, int H, int W, int C, in
 hipError_t nn_relu_mask(const float* dout, const unsigned short* out, int relu, unsigned short* g,
                         float* dbias, size_t n, int C, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_relu_mask, dim3(nblocks(n)), dim3(256), C * sizeof(float), s, dout, out, relu, g, dbias,
-                       n, C);
+    // at most 1024 workgroups: each adds C partial sums into dbias with
+    // global atomics, which contend on the C addresses
+    const dim3 grid(std::min(nblocks(n), 1024u));
+    if (C >= 1 && C <= 256 && (C & (C - 1)) == 0)   // C divides the grid stride (a multiple of 256)
+        hipLaunchKernelGGL(k_relu_mask_pc, grid, dim3(256), C * sizeof(float), s, dout, out, relu, g, dbias, n, C);
+    else
+        hipLaunchKernelGGL(k_relu_mask, grid, dim3(256), C * sizeof(float), s, dout, out, relu, g, dbias, n, C);
     return hipGetLastError();
 }
 
 hipError_t nn_mse(const float* x, const float* t, float* g, double* loss, size_t n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mse, dim3(nblocks(n)), dim3(256), 0, s, x, t, g, loss, n);
+    // at most 1024 workgroups: each adds its partial loss with one FP64 atomic
+    hipLaunchKernelGGL(k_mse, dim3(std::min(nblocks(n), 1024u)), dim3(256), 0, s, x, t, g, loss, n);
     return hipGetLastError();
 }
 
@@ -482,7 +517,7 @@ hipError_t nn_adam(float* w, float* g, float* m, float* v, size_t n, float lr, f
 hipError_t nn_prep_input(const float* x, unsigned short* y, unsigned int* scratch, size_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, scratch, (size_t)1, 0u);
-    hipLaunchKernelGGL(k_absmax, dim3(nblocks(n)), dim3(256), 0, s, x, n, scratch);
+    hipLaunchKernelGGL(k_absmax, dim3(std::min(nblocks(n), 1024u)), dim3(256), 0, s, x, n, scratch);
     hipLaunchKernelGGL(k_scale_to_bf16, dim3(nblocks(n)), dim3(256), 0, s, x, scratch, y, n);
     return hipGetLastError();
 }
