@@ -110,6 +110,92 @@ __global__ __launch_bounds__(kBlock) void k_major_fwd_w(XportDev d, float* __res
     }
 }
 
+// R consecutive floats of an LDS row group (16-, 8- or 4-byte aligned).
+template <int R>
+__device__ __forceinline__ void lds_rows(const float* p, float (&v)[R])
+{
+    if constexpr (R % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < R; i += 4) {
+            const float4 q = *reinterpret_cast<const float4*>(p + i);
+            v[i] = q.x; v[i + 1] = q.y; v[i + 2] = q.z; v[i + 3] = q.w;
+        }
+    } else if constexpr (R == 2) {
+        const float2 q = *reinterpret_cast<const float2*>(p);
+        v[0] = q.x; v[1] = q.y;
+    } else {
+        v[0] = p[0];
+    }
+}
+
+constexpr int kBlockF = 1024;   // LDS-staged major passes: 16 waves share one staged block
+constexpr int kGroup = 4;       // plenoptic stage 1: terms of kGroup slices summed in FP32, then in FP64
+
+// k_major_fwd with the intermediate staged in LDS: a workgroup of kBlockF
+// threads takes R detector rows and kBlockF detector columns; per chunk of zc
+// (slice, angular row) pairs it stages the R rows of every pair once
+// (coalesced; the R rows of one voxel column adjacent so one LDS read serves
+// all R; W - 1 zero columns past the last so the band needs no clamp), and a
+// thread applies its column's band weights, loaded once per pair, to the R
+// staged rows.  Each product is rounded to FP32 and summed in FP64, as in
+// the adjoint's passes, so that A and A^T round the same products alike.
+// W is the table's width.
+template <int R, int W>
+__global__ __launch_bounds__(kBlockF) void k_major_fwd_lds(XportDev d, float* __restrict__ y, int zc)
+{
+    extern __shared__ float4 ms4[];
+    float* ms = reinterpret_cast<float*>(ms4);             // [pair of the chunk][nx + W - 1][R]
+    const int nvb = (d.nv + R - 1) / R;
+    const int v0 = (blockIdx.x % nvb) * R;
+    const int u = (blockIdx.x / nvb) * kBlockF + threadIdx.x;
+    const bool live = u < d.nu;
+    const int nr = min(R, d.nv - v0);
+    const int pairs = d.nz * d.kt;
+    const int pitch = (d.nx + W - 1) * R;                  // floats per staged pair
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0;
+    const int lane = threadIdx.x & 63;
+    for (int p0 = 0; p0 < pairs; p0 += zc) {
+        const int npc = min(zc, pairs - p0);
+        __syncthreads();                                   // the previous chunk is consumed
+        // one wave per staged row, lanes along it; loads from clamped (valid)
+        // addresses, then a select, so a wave's loads are in flight together
+        for (int row = threadIdx.x >> 6; row < npc * R; row += kBlockF / 64) {
+            const int p = row / R, r = row % R;
+            const float* src = d.mid + ((size_t)(p0 + p) * d.nv + v0 + min(r, nr - 1)) * d.nx;
+            float* dst = ms + p * pitch + r;
+#pragma unroll 4
+            for (int ix = lane; ix < d.nx + W - 1; ix += 64) {
+                const float v = src[min(ix, d.nx - 1)];
+                dst[ix * R] = r < nr && ix < d.nx ? v : 0.0f;
+            }
+        }
+        __syncthreads();
+        if (!live) continue;
+#pragma unroll 4
+        for (int p = 0; p < npc; ++p) {
+            // 32-bit table offsets (the launcher checks the tables' sizes)
+            const int pp = p0 + p;
+            const int s0 = d.cs.start[pp * d.nu + u];
+            const int wo = pp * W * d.nu + u;
+            const float* mz = ms + p * pitch + s0 * R;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const float wk = d.cs.w[wo + k * d.nu];
+                float m[R];
+                lds_rows<R>(mz + k * R, m);
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[r] += (double)(wk * m[r]);
+            }
+        }
+    }
+    if (!live) return;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (r < nr) y[(size_t)(v0 + r) * d.nu + u] = (float)acc[r];
+}
+
 // Same as k_major_adj with the loop bound fixed at compile time (W >= the
 // table's width; the terms past the width are skipped).
 template <int W>
@@ -142,7 +228,8 @@ __global__ __launch_bounds__(kBlock) void k_major_adj_w(XportDev d, const float*
 // `rows` detector rows (staged once, coalesced) and a chunk of (slice, row)
 // pairs; a thread holds one (pair, voxel column)'s band weights in registers
 // and applies them to every staged row.  The image gathers hit LDS instead
-// of scattered global loads.  W >= the table's width (terms past it skipped).
+// of scattered global loads.  W >= the table's width (terms past it
+// skipped).
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_major_adj_lds(XportDev d, const float* __restrict__ y,
                                                           int rows, int pchunk)
@@ -327,6 +414,24 @@ hipError_t launch_xport_project(const XportDev& d, const float* x, float* y, hip
     hipLaunchKernelGGL(k_minor_fwd, dim3(grid_for(nm)), dim3(kBlock), 0, s, d, x);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    // LDS-staged pass for band widths up to 4 while 4 rows of one pair fit 64 KiB
+    {
+        constexpr int R = 4;
+        const int w = std::max(1, d.cs.width);
+        const int zc = 65536 / ((d.nx + w - 1) * R * (int)sizeof(float));
+        const int nvb = (d.nv + R - 1) / R, nub = (d.nu + kBlockF - 1) / kBlockF;
+        const size_t lds = (size_t)std::max(1, zc) * (d.nx + w - 1) * R * sizeof(float);
+        const dim3 gs((unsigned)((size_t)nvb * nub)), bf(kBlockF);
+        if (zc >= 1 && d.cs.width <= 4 && (size_t)d.nz * d.kt * d.cs.width * d.nu < (1u << 31)) {
+            switch (d.cs.width) {
+            case 1: hipLaunchKernelGGL((k_major_fwd_lds<R, 1>), gs, bf, lds, s, d, y, zc); break;
+            case 2: hipLaunchKernelGGL((k_major_fwd_lds<R, 2>), gs, bf, lds, s, d, y, zc); break;
+            case 3: hipLaunchKernelGGL((k_major_fwd_lds<R, 3>), gs, bf, lds, s, d, y, zc); break;
+            default: hipLaunchKernelGGL((k_major_fwd_lds<R, 4>), gs, bf, lds, s, d, y, zc); break;
+            }
+            return hipGetLastError();
+        }
+    }
     const size_t ny = (size_t)((d.nv + kRowsPerThread - 1) / kRowsPerThread) * d.nu;
     const dim3 g(grid_for(ny)), b(kBlock);
     switch (d.cs.width) {
@@ -453,23 +558,6 @@ __global__ __launch_bounds__(kBlock) void k_pl_major1_w(PlenDev d)
     }
 }
 
-// R consecutive floats of an LDS row group (16-, 8- or 4-byte aligned).
-template <int R>
-__device__ __forceinline__ void lds_rows(const float* p, float (&v)[R])
-{
-    if constexpr (R % 4 == 0) {
-#pragma unroll
-        for (int i = 0; i < R; i += 4) {
-            const float4 q = *reinterpret_cast<const float4*>(p + i);
-            v[i] = q.x; v[i + 1] = q.y; v[i + 2] = q.z; v[i + 3] = q.w;
-        }
-    } else if constexpr (R == 2) {
-        const float2 q = *reinterpret_cast<const float2*>(p);
-        v[0] = q.x; v[1] = q.y;
-    } else {
-        v[0] = p[0];
-    }
-}
 
 // k_pl_major1 with the intermediate staged in LDS: a workgroup of kBlockF
 // threads takes R array rows of one angular row kt and kBlockF output columns
@@ -480,9 +568,6 @@ __device__ __forceinline__ void lds_rows(const float* p, float (&v)[R])
 // applies its column's band weights, loaded once per slice, to the R staged
 // rows.  Sums: FP32 over the terms of kGroup consecutive slices, FP64 across
 // groups.  W is the table's width.
-constexpr int kBlockF = 1024;
-constexpr int kGroup = 4;
-
 template <int R, int W>
 __global__ __launch_bounds__(kBlockF) void k_pl_major1_lds(PlenDev d, int zc, int ncb)
 {
