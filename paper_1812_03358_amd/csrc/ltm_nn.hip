@@ -72,14 +72,14 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a)
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < a.Kp; k0 += 32) {
-        const int kk = k0 + 8 * kg;
-        Frag A[MT];
+    if (CIN1) {
+        for (int k0 = 0; k0 < a.Kp; k0 += 32) {
+            const int kk = k0 + 8 * kg;
+            Frag A[MT];
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            A[m].q = uint4{0u, 0u, 0u, 0u};
-            if (!vin[m]) continue;
-            if (CIN1) {
+            for (int m = 0; m < MT; ++m) {
+                A[m].q = uint4{0u, 0u, 0u, 0u};
+                if (!vin[m]) continue;
                 // one input channel: the 8 K values are 8 taps
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
@@ -92,27 +92,59 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a)
                     const size_t src = ((size_t)(z >> a.up) * Hin + (y >> a.up)) * Win + (x >> a.up);
                     A[m].h[j] = a.in0[src];
                 }
-            } else {
-                const int tap = kk / cin, ci = kk - tap * cin;
-                if (tap >= taps) continue;
-                const int dz = KS == 3 ? tap / 9 - 1 : 0, dy = KS == 3 ? (tap / 3) % 3 - 1 : 0,
-                          dx = KS == 3 ? tap % 3 - 1 : 0;
-                const int z = vz[m] + dz, y = vy[m] + dy, x = vx[m] + dx;
-                if (z < 0 || z >= a.D || y < 0 || y >= a.H || x < 0 || x >= a.W) continue;
-                const size_t src = ((size_t)(z >> a.up) * Hin + (y >> a.up)) * Win + (x >> a.up);
-                if (ci < a.c0)
-                    A[m].q = *reinterpret_cast<const uint4*>(a.in0 + src * a.c0 + ci);
-                else
-                    A[m].q = *reinterpret_cast<const uint4*>(a.in1 + src * a.c1 + (ci - a.c0));
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                Frag B;
+                B.q = *reinterpret_cast<const uint4*>(a.wt + (size_t)(t * 16 + r) * a.Kp + kk);
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+                    acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[m].v, B.v, acc[m][t], 0, 0, 0);
             }
         }
+    } else {
+        // U K-steps at a time: all their operand loads are issued before
+        // their MFMAs.  Loads are branch-free: an out-of-range tap or voxel
+        // reads a valid address and selects zero; a K-step past Kp repeats
+        // step k0 and is skipped.
+        constexpr int U = 2;
+        for (int k0 = 0; k0 < a.Kp; k0 += 32 * U) {
+            Frag A[U][MT], B[U][NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            Frag B;
-            B.q = *reinterpret_cast<const uint4*>(a.wt + (size_t)(t * 16 + r) * a.Kp + kk);
+            for (int u = 0; u < U; ++u) {
+                const int kk = (k0 + 32 * u < a.Kp ? k0 + 32 * u : k0) + 8 * kg;
+                const int tap = kk / cin, ci = kk - tap * cin;
+                const bool tapok = tap < taps;
+                const int dz = KS == 3 ? tap / 9 - 1 : 0, dy = KS == 3 ? (tap / 3) % 3 - 1 : 0,
+                          dx = KS == 3 ? tap % 3 - 1 : 0;
+                // the 8 channels [ci, ci + 8) lie in one input (c0 % 8 == 0)
+                const bool first = ci < a.c0;
+                const u16* src_base = first ? a.in0 + ci : a.in1 + (ci - a.c0);
+                const int cst = first ? a.c0 : a.c1;
 #pragma unroll
-            for (int m = 0; m < MT; ++m)
-                acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[m].v, B.v, acc[m][t], 0, 0, 0);
+                for (int m = 0; m < MT; ++m) {
+                    const int z = vz[m] + dz, y = vy[m] + dy, x = vx[m] + dx;
+                    const bool ok = vin[m] && tapok && (unsigned)z < (unsigned)a.D &&
+                                    (unsigned)y < (unsigned)a.H && (unsigned)x < (unsigned)a.W;
+                    const size_t src =
+                        ok ? ((size_t)(z >> a.up) * Hin + (y >> a.up)) * Win + (x >> a.up) : 0;
+                    const uint4 q = *reinterpret_cast<const uint4*>(src_base + src * cst);
+                    A[u][m].q = ok ? q : uint4{0u, 0u, 0u, 0u};
+                }
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    B[u][t].q = *reinterpret_cast<const uint4*>(a.wt + (size_t)(t * 16 + r) * a.Kp + kk);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (k0 + 32 * u >= a.Kp) break;
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int m = 0; m < MT; ++m)
+                        acc[m][t] =
+                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[u][m].v, B[u][t].v, acc[m][t], 0, 0, 0);
+            }
         }
     }
     // epilogue: bias, ReLU, store (BF16 or FP32, optionally split in two
@@ -173,7 +205,11 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a)
     const int zz = z + dz;
     const bool zin = kvalid && zz >= 0 && zz < a.D;
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int v0 = 0; v0 < HW; v0 += 32) {
+    // this workgroup's share of the slice (gridDim.z shares of 32-voxel groups)
+    const int ngroups = (HW + 31) / 32;
+    const int g0 = (int)(((long long)ngroups * blockIdx.z) / gridDim.z);
+    const int g1 = (int)(((long long)ngroups * (blockIdx.z + 1)) / gridDim.z);
+    for (int v0 = g0 * 32; v0 < g1 * 32; v0 += 32) {
         Frag A, B;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -199,6 +235,98 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a)
     for (int i = 0; i < 4; ++i) {
         const int c = cot * 16 + 4 * kg + i;
         if (c < a.cout && acc[i] != 0.0f) unsafeAtomicAdd(&a.dw[(size_t)c * a.K + kc], acc[i]);
+    }
+}
+
+// k_conv_wgrad for grids whose H and W are powers of two (H W a multiple of
+// 32) and cout a multiple of 16: voxel coordinates by shifts, no branches in
+// the operand loads (an out-of-range tap reads a valid address and selects
+// zero), the input base pointer and channel stride of each lane hoisted, and
+// each wave owning NK k-tiles of one output-channel tile, so one dY fragment
+// feeds NK MFMAs.
+template <int KS, int NK>
+__global__ __launch_bounds__(256) void k_conv_wgrad_pow2(ConvWgrad a, int lw, int lh)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, kg = lane >> 4;
+    const int n_co = a.cout >> 4;
+    const int n_kg = ((a.K + 15) / 16 + NK - 1) / NK;
+    const int tile = blockIdx.x * 4 + wave;
+    if (tile >= n_co * n_kg) return;
+    const int cot = tile % n_co, kgi = tile / n_co;
+    const int z = blockIdx.y;
+    const int W = 1 << lw, H = 1 << lh, HW = W * H;
+    const int Hin = H >> a.up, Win = W >> a.up;
+    const int cin = a.c0 + a.c1;
+    const u16* dyz = a.dy + (size_t)z * HW * a.cout + cot * 16 + r;
+    // per k-tile: this lane's B column k = tap * cin + ci
+    const u16* base[NK];
+    int cst[NK], ddy[NK], ddx[NK], zoff[NK];
+    bool live[NK];
+#pragma unroll
+    for (int t = 0; t < NK; ++t) {
+        const int k = (kgi * NK + t) * 16 + r;
+        const bool kv = k < a.K;
+        const int tap = kv ? k / cin : 0, ci = kv ? k - tap * cin : 0;
+        const int dz = KS == 3 ? tap / 9 - 1 : 0;
+        ddy[t] = KS == 3 ? (tap / 3) % 3 - 1 : 0;
+        ddx[t] = KS == 3 ? tap % 3 - 1 : 0;
+        const int zz = z + dz;
+        live[t] = kv && zz >= 0 && zz < a.D;
+        zoff[t] = live[t] ? (zz >> a.up) * Hin * Win : 0;
+        base[t] = ci < a.c0 ? a.in0 + ci : a.in1 + (ci - a.c0);
+        cst[t] = ci < a.c0 ? a.c0 : a.c1;
+    }
+    f32x4 acc[NK];
+#pragma unroll
+    for (int t = 0; t < NK; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // a wave walks a whole slice, U voxel groups at a time: all their loads
+    // are issued before their MFMAs (a group past the slice loads group 0
+    // and is skipped)
+    constexpr int U = 4;
+    // this workgroup's share of the slice's voxel groups (gridDim.z shares)
+    const int ngroups = HW >> 5;
+    const int sb = (int)(((long long)ngroups * blockIdx.z) / gridDim.z);
+    const int nsteps = (int)(((long long)ngroups * (blockIdx.z + 1)) / gridDim.z);
+    for (int s0 = sb; s0 < nsteps; s0 += U) {
+        Frag A[U], B[U][NK];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int vb = (s0 + u < nsteps ? s0 + u : sb) * 32 + 8 * kg;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) A[u].h[j] = dyz[(size_t)(vb + j) * a.cout];
+            const int y0 = vb >> lw, x0 = vb & (W - 1);   // the 8 voxels share a row (W >= 8)
+#pragma unroll
+            for (int t = 0; t < NK; ++t) {
+                const int y = y0 + ddy[t];
+                const bool rowok = live[t] && (unsigned)y < (unsigned)H;
+                const int rowoff = zoff[t] + (rowok ? (y >> a.up) : 0) * Win;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int x = x0 + j + ddx[t];
+                    const bool ok = rowok && (unsigned)x < (unsigned)W;
+                    const u16 val = base[t][(size_t)(rowoff + (ok ? (x >> a.up) : 0)) * cst[t]];
+                    B[u][t].h[j] = ok ? val : (u16)0;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (s0 + u >= nsteps) break;
+#pragma unroll
+            for (int t = 0; t < NK; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[u].v, B[u][t].v, acc[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NK; ++t) {
+        const int kc = (kgi * NK + t) * 16 + r;
+        if (kc >= a.K) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int c = cot * 16 + 4 * kg + i;
+            if (acc[t][i] != 0.0f) unsafeAtomicAdd(&a.dw[(size_t)c * a.K + kc], acc[t][i]);
+        }
     }
 }
 
@@ -446,8 +574,26 @@ hipError_t nn_conv_fwd(const ConvFwd& a, int ks, hipStream_t s)
 
 hipError_t nn_conv_wgrad(const ConvWgrad& a, int ks, hipStream_t s)
 {
+    auto lg2 = [](int n) { int l = 0; while ((1 << l) < n) ++l; return (1 << l) == n ? l : -1; };
+    const int lw = lg2(a.W), lh = lg2(a.H);
+    if (ks == 3 && lw >= 3 && lh >= 0 && (a.W * a.H) % 32 == 0 && a.cout % 16 == 0 &&
+        (!a.up || (a.W % 2 == 0 && a.H % 2 == 0))) {
+        constexpr int NK = 2;
+        const int tiles = (a.cout / 16) * (((a.K + 15) / 16 + NK - 1) / NK);
+        // split each slice's voxel groups over workgroups until ~8192 waves
+        // run (one per tile, slice and share); each share adds its own
+        // partial sums into dw
+        const int blocks = (tiles + 3) / 4 * a.D;
+        const int groups = a.W * a.H / 32;
+        const int shares = std::max(1, std::min(groups, 2048 / std::max(1, blocks)));
+        hipLaunchKernelGGL((k_conv_wgrad_pow2<3, NK>), dim3((tiles + 3) / 4, a.D, shares), dim3(256), 0, s, a,
+                           lw, lh);
+        return hipGetLastError();
+    }
     const int tiles = ((a.cout + 15) / 16) * ((a.K + 15) / 16);
-    dim3 grid((tiles + 3) / 4, a.D);
+    const int blocks = (tiles + 3) / 4 * a.D;
+    const int shares = std::max(1, std::min((a.W * a.H + 31) / 32, 2048 / std::max(1, blocks)));
+    dim3 grid((tiles + 3) / 4, a.D, shares);
     if (ks == 3)
         hipLaunchKernelGGL(k_conv_wgrad<3>, grid, dim3(256), 0, s, a);
     else
