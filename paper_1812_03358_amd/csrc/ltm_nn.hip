@@ -180,8 +180,9 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a)
 // dW[co][k] += sum_v dY[v][co] X_k[v], k = tap * Cin + ci, X_k the input
 // shifted by the tap (and upsampled when up = 1).  MFMA rows are output
 // channels, columns are k, the reduction runs over 32 voxels of one output
-// z-slice at a time.  A workgroup's 4 waves own 4 (co, k) tiles of one slice
-// and add them into the FP32 gradient with atomics.
+// z-slice at a time.  A workgroup's 4 waves own 4 (co, k) tiles of one share
+// of one slice (gridDim.z shares of its 32-voxel groups) and add them into
+// the FP32 gradient with atomics.
 template <int KS>
 __global__ __launch_bounds__(256) void k_conv_wgrad(ConvWgrad a)
 {
