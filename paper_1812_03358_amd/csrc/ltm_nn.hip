@@ -176,6 +176,104 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a)
         }
 }
 
+// 3x3x3 convolution with at most 64 input channels, its input tile staged
+// in LDS: a workgroup computes a 16 x 4 x TZ (x, y, z) block of output voxels
+// (wave w: row y0 + w, its TZ tiles the TZ z planes, 16 voxels along x each)
+// and stages the block's input halo (18 x 6 x (TZ + 2) voxels, all channels,
+// zero outside the grid; the upsampled and the concatenated inputs resolved
+// while staging) once, so each A fragment is one 16-byte LDS read instead of
+// a global gather.  K runs over (tap, channel) as in the packed weights.
+constexpr int kTX = 16, kTY = 4;
+constexpr int kHX = kTX + 2, kHY = kTY + 2;
+
+template <int NT, int TZ>
+__global__ __launch_bounds__(256) void k_conv_fwd_lds(ConvFwd a)
+{
+    constexpr int kTZ = TZ, kHZ = TZ + 2;
+    extern __shared__ uint4 hs4[];
+    u16* hs = reinterpret_cast<u16*>(hs4);                 // [kHZ][kHY][kHX][cin]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, kg = lane >> 4;
+    const int cin = a.c0 + a.c1;
+    const int Din = a.D >> a.up, Hin = a.H >> a.up, Win = a.W >> a.up;
+    const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, z0 = blockIdx.z * kTZ;
+    // stage the halo in 8-channel groups (16 bytes; c0 and c1 are multiples of 8)
+    const int groups = cin >> 3;
+    for (int i = threadIdx.x; i < kHX * kHY * kHZ * groups; i += 256) {
+        const int g = i % groups, vox = i / groups;
+        const int hx = vox % kHX, hy = (vox / kHX) % kHY, hz = vox / (kHX * kHY);
+        const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+        const bool ok = (unsigned)x < (unsigned)a.W && (unsigned)y < (unsigned)a.H && (unsigned)z < (unsigned)a.D;
+        const int xc = ok ? x : 0, yc = ok ? y : 0, zc = ok ? z : 0;
+        const int ci = g * 8;
+        const u16* src = ci < a.c0
+            ? a.in0 + (((size_t)(zc >> a.up) * Hin + (yc >> a.up)) * Win + (xc >> a.up)) * a.c0 + ci
+            : a.in1 + (((size_t)zc * a.H + yc) * a.W + xc) * a.c1 + (ci - a.c0);
+        const uint4 q = *reinterpret_cast<const uint4*>(src);
+        *reinterpret_cast<uint4*>(hs + (size_t)vox * cin + ci) = ok ? q : uint4{0u, 0u, 0u, 0u};
+    }
+    (void)Din;
+    __syncthreads();
+    f32x4 acc[kTZ][NT];
+#pragma unroll
+    for (int m = 0; m < kTZ; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int nsteps = a.Kp >> 5;
+    for (int ks = 0; ks < nsteps; ++ks) {
+        const int k = ks * 32 + 8 * kg;
+        const int tap = k / cin, ci = k - tap * cin;
+        const bool tapok = tap < 27;
+        const int tp = tapok ? tap : 0;
+        const int dz = tp / 9 - 1, dy = (tp / 3) % 3 - 1, dx = tp % 3 - 1;
+        Frag B[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            B[t].q = *reinterpret_cast<const uint4*>(a.wt + (size_t)(t * 16 + r) * a.Kp + k);
+        const int hxy = ((1 + wave + dy) * kHX + (1 + r + dx));
+#pragma unroll
+        for (int m = 0; m < kTZ; ++m) {
+            Frag A;
+            const uint4 q = *reinterpret_cast<const uint4*>(
+                hs + (size_t)(((1 + m + dz) * kHY * kHX) + hxy) * cin + ci);
+            A.q = tapok ? q : uint4{0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.v, B[t].v, acc[m][t], 0, 0, 0);
+        }
+    }
+    // epilogue: output row 4 kg + i of tile m is voxel (x0 + 4 kg + i, y0 + wave, z0 + m)
+    const int y = y0 + wave;
+#pragma unroll
+    for (int m = 0; m < kTZ; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int co = t * 16 + r;
+            if (co >= a.cout) continue;
+            const int z = z0 + m;
+            if (z >= a.D || y >= a.H) continue;
+            const float b = a.bias ? a.bias[co] : 0.0f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = x0 + 4 * kg + i;
+                if (x >= a.W) continue;
+                const size_t v = ((size_t)z * a.H + y) * a.W + x;
+                float val = acc[m][t][i] + b;
+                if (a.relu) val = fmaxf(val, 0.0f);
+                if (co < a.split) {
+                    const size_t o = v * a.split + co;
+                    if (a.out_f32) reinterpret_cast<float*>(a.out)[o] = val;
+                    else reinterpret_cast<u16*>(a.out)[o] = f2bf(val);
+                } else {
+                    const int c2 = a.cout - a.split;
+                    const size_t o = v * c2 + (co - a.split);
+                    if (a.out_f32) reinterpret_cast<float*>(a.out2)[o] = val;
+                    else reinterpret_cast<u16*>(a.out2)[o] = f2bf(val);
+                }
+            }
+        }
+}
+
 // ---------------------------------------------------------------- wgrad
 // dW[co][k] += sum_v dY[v][co] X_k[v], k = tap * Cin + ci, X_k the input
 // shifted by the tap (and upsampled when up = 1).  MFMA rows are output
@@ -568,7 +666,30 @@ hipError_t nn_conv_fwd(const ConvFwd& a, int ks, hipStream_t s)
 {
     const int nt = (a.cout + 15) / 16;
     const int ntp = nt <= 1 ? 1 : (nt <= 2 ? 2 : (nt <= 4 ? 4 : 8));
-    const bool cin1 = (a.c0 + a.c1) == 1;
+    const int cin = a.c0 + a.c1;
+    const bool cin1 = cin == 1;
+    if (ks == 3 && cin >= 8 && cin <= 64 && cin % 8 == 0) {
+        // 4 output planes per workgroup up to 32 channels (41 KiB halo), 2 up to 64 (55 KiB)
+        const int tz = cin <= 32 ? 4 : 2;
+        const dim3 g((a.W + kTX - 1) / kTX, (a.H + kTY - 1) / kTY, (a.D + tz - 1) / tz);
+        const size_t lds = (size_t)kHX * kHY * (tz + 2) * cin * sizeof(unsigned short);
+        if (tz == 4) {
+            switch (ntp) {
+            case 1: hipLaunchKernelGGL((k_conv_fwd_lds<1, 4>), g, dim3(256), lds, s, a); break;
+            case 2: hipLaunchKernelGGL((k_conv_fwd_lds<2, 4>), g, dim3(256), lds, s, a); break;
+            case 4: hipLaunchKernelGGL((k_conv_fwd_lds<4, 4>), g, dim3(256), lds, s, a); break;
+            default: hipLaunchKernelGGL((k_conv_fwd_lds<8, 4>), g, dim3(256), lds, s, a); break;
+            }
+        } else {
+            switch (ntp) {
+            case 1: hipLaunchKernelGGL((k_conv_fwd_lds<1, 2>), g, dim3(256), lds, s, a); break;
+            case 2: hipLaunchKernelGGL((k_conv_fwd_lds<2, 2>), g, dim3(256), lds, s, a); break;
+            case 4: hipLaunchKernelGGL((k_conv_fwd_lds<4, 2>), g, dim3(256), lds, s, a); break;
+            default: hipLaunchKernelGGL((k_conv_fwd_lds<8, 2>), g, dim3(256), lds, s, a); break;
+            }
+        }
+        return hipGetLastError();
+    }
     if (ks == 3) return cin1 ? conv_nt<3, true>(a, ntp, s) : conv_nt<3, false>(a, ntp, s);
     return cin1 ? conv_nt<1, true>(a, ntp, s) : conv_nt<1, false>(a, ntp, s);
 }
