@@ -370,7 +370,9 @@ def _plenoptic_parts(g: dict, cam: dict, basis: int, ka):
     if cam["kind"] != 1:
         raise ValueError("the factorized model is for square-array plenoptic cameras")
     _check_head_on(dict(cam, kind=0))
-    nx, ny, nz, dx = g["nx"], g["ny"], g["nz"], g["pitch"]
+    nx, ny, nz = g["nx"], g["ny"], g["nz"]
+    pitch = g["pitch"]
+    hx, hy, dz = (pitch, pitch, pitch) if np.isscalar(pitch) else pitch   # s, t, depth sizes
     nu, nv, mu, mv = cam["det_nu"], cam["det_nv"], cam["mla_nu"], cam["mla_nv"]
     k = nu // mu
     ka = k if ka is None else ka
@@ -381,8 +383,8 @@ def _plenoptic_parts(g: dict, cam: dict, basis: int, ka):
     cells, d0s, d0t = angular_cells(cam)
     sa = (np.arange(na_u) + 0.5 - 0.5 * na_u) * da
     ta = (np.arange(na_v) + 0.5 - 0.5 * na_v) * da
-    sj = (np.arange(nx) + 0.5 - 0.5 * nx) * dx
-    tj = (np.arange(ny) + 0.5 - 0.5 * ny) * dx
+    sj = (np.arange(nx) + 0.5 - 0.5 * nx) * hx
+    tj = (np.arange(ny) + 0.5 - 0.5 * ny) * hy
     sd = (np.arange(nu) + 0.5 - 0.5 * nu) * cam["pixel_pitch"]
     td = (np.arange(nv) + 0.5 - 0.5 * nv) * cam["pixel_pitch"]
     cu = (np.arange(mu) + 0.5 - 0.5 * mu) * P
@@ -401,11 +403,11 @@ def _plenoptic_parts(g: dict, cam: dict, basis: int, ka):
     for (sk, tk) in cells:
         per = []
         for iz in range(nz):
-            zq = L + (iz + 0.5 - 0.5 * nz) * dx
+            zq = L + (iz + 0.5 - 0.5 * nz) * dz
             X0q = np.linalg.inv(T(zq) @ R(cam["f_main"]))
             Xaq = np.linalg.inv(X0a) @ X0q
-            per.append((transport_factor(basis, Xaq, X0q, sk, d0s, sa, da, sj, dx),
-                        transport_factor(basis, Xaq, X0q, tk, d0t, ta, da, tj, dx)))
+            per.append((transport_factor(basis, Xaq, X0q, sk, d0s, sa, da, sj, hx),
+                        transport_factor(basis, Xaq, X0q, tk, d0t, ta, da, tj, hy)))
         stage1.append(per)
         Bs2 = np.zeros((nu, na_u))
         Bt2 = np.zeros((nv, na_v))
@@ -420,7 +422,7 @@ def _plenoptic_parts(g: dict, cam: dict, basis: int, ka):
             Bt2[:, vs] = transport_factor(basis, np.linalg.inv(X0d_t) @ X0a, X0a, tk, d0t, td,
                                           cam["pixel_pitch"], ta[vs], da)
         stage2.append((Bs2, Bt2))
-    return dict(inside=inside, Va=Va, Vd=Vd, norm=norm, dx=dx, stage1=stage1, stage2=stage2,
+    return dict(inside=inside, Va=Va, Vd=Vd, norm=norm, dz=dz, stage1=stage1, stage2=stage2,
                 shape_a=(na_v, na_u), shape_d=(nv, nu), shape_x=(nz, ny, nx))
 
 
@@ -445,7 +447,7 @@ def project_plenoptic(g: dict, cam: dict, x, basis: int = PILLBOX, ka: int | Non
     for per, (Bs2, Bt2) in zip(Pp["stage1"], Pp["stage2"]):
         fa = np.zeros(Pp["shape_a"])
         for iz, (Bs, Bt) in enumerate(per):
-            fa += Bt @ (Pp["dx"] * x[iz]) @ Bs.T
+            fa += Bt @ (Pp["dz"] * x[iz]) @ Bs.T
         fa = fa / Pp["Va"] * Pp["inside"]
         y += Bt2 @ fa @ Bs2.T / Pp["Vd"]
     return (y * Pp["norm"]).reshape(-1)
@@ -460,5 +462,29 @@ def backproject_plenoptic(g: dict, cam: dict, y, basis: int = PILLBOX, ka: int |
         fa = Bt2.T @ y @ Bs2 / Pp["Vd"]
         fa = fa / Pp["Va"] * Pp["inside"]
         for iz, (Bs, Bt) in enumerate(per):
-            x[iz] += Pp["dx"] * (Bt.T @ fa @ Bs)
+            x[iz] += Pp["dz"] * (Bt.T @ fa @ Bs)
     return x.reshape(-1)
+
+
+def _head_on_view(cam: dict):
+    """The camera in its own axes (lens on the z axis at its distance)."""
+    return dict(cam, axes=[1.0, 0, 0, 0, 1.0, 0, 0, 0, 1.0],
+                lens_center=[0.0, 0.0, -_camera_distance(cam)])
+
+
+def project_plenoptic_posed(g: dict, cam: dict, x, basis: int = PILLBOX, ka: int | None = None):
+    """A x of the factorized plenoptic model for a square-array plenoptic
+    camera at azimuth phi (|phi| <= 45 deg): the coefficients rotated into
+    the camera's axes (scaling and two shears), then the head-on factorized
+    transport on the rotated grid's anisotropic voxels."""
+    xr, Rg = rotate_azimuth(g, x, cam["phi_deg"])
+    gr = dict(nx=Rg["nx"], ny=Rg["ny"], nz=Rg["nz"], pitch=(Rg["hx"], Rg["hy"], Rg["hz"]))
+    return project_plenoptic(gr, _head_on_view(cam), xr, basis, ka)
+
+
+def backproject_plenoptic_posed(g: dict, cam: dict, y, basis: int = PILLBOX, ka: int | None = None):
+    """A^T y of ``project_plenoptic_posed``."""
+    Rg = rotated_grid(g, cam["phi_deg"])
+    gr = dict(nx=Rg["nx"], ny=Rg["ny"], nz=Rg["nz"], pitch=(Rg["hx"], Rg["hy"], Rg["hz"]))
+    xr = backproject_plenoptic(gr, _head_on_view(cam), y, basis, ka)
+    return rotate_azimuth_adjoint(g, xr, cam["phi_deg"]).reshape(-1)
