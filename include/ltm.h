@@ -396,8 +396,9 @@ ltm_status ltm_nn_add(float* a, const float* b, uint64_t n, void* stream);
  * The library evaluates the entries in FP64 once, at bind time, into banded
  * FP32 tables in the workspace.
  *
- * A head-on square-array plenoptic camera (LTM_PLENOPTIC, phi = 0) takes
- * the paper's factorized plenoptic model instead: every slice is transported
+ * A square-array plenoptic camera (LTM_PLENOPTIC, posed as above, the
+ * volume rotated the same way) takes the paper's factorized plenoptic model
+ * instead: every slice is transported
  * onto the lenslet-array plane (d_mla behind the main lens; array pixels of
  * the detector's pitch, det_nu / mla_nu per lenslet) per angular cell; the
  * aperture mask keeps array pixels whose centre lies inside their lenslet's
@@ -411,7 +412,7 @@ ltm_status ltm_nn_add(float* a, const float* b, uint64_t n, void* stream);
  * bounding square.  Workspace: the tables plus three FP32 intermediates,
  * nz * rays_v * det_nv * nx (slices filtered along t), cells * det_nv *
  * det_nu (the masked array-plane light field), and the same again (after
- * the lenslet t stage). */
+ * the lenslet t stage), plus the two rotated volumes of a posed camera. */
 enum { LTM_BASIS_DIRAC = 0u, LTM_BASIS_PILLBOX = 1u };
 
 typedef struct ltm_xport ltm_xport;

@@ -275,27 +275,69 @@ using namespace ltm;
 
 namespace {
 
+// Rotation of a posed camera's volume into its axes: the z shear E^z per
+// natural x column (shift sa x, spread |sa| hx) and the x shear E^x per
+// sheared z row (shift sb z, spread |sb| hz), with exact transposes.
+void build_shears(ltm_xport* t, const ltm_grid* g, double sa, double sb, double hx, double hz)
+{
+    const int nx1 = (int)g->nx, nz1 = (int)g->nz, nzr = t->nzr, nxr = t->nxr;
+    std::vector<Rows> ezp, exp_;
+    for (int x1 = 0; x1 < nx1; ++x1)
+        ezp.push_back(shear_rows(nzr, nz1, hz, sa * (x1 + 0.5 - 0.5 * nx1) * hx, std::fabs(sa) * hx));
+    for (int z = 0; z < nzr; ++z)
+        exp_.push_back(shear_rows(nxr, nx1, hx, sb * (z + 0.5 - 0.5 * nzr) * hz, std::fabs(sb) * hz));
+    pack(ezp, nzr, t->ez);
+    pack(exp_, nxr, t->ex);
+    transpose(t->ez, nx1, nz1, t->ezt);
+    transpose(t->ex, nzr, nx1, t->ext);
+}
+
+// Workspace places of the shear tables and the two rotated volumes.
+void place_shears(ltm_xport* t, const ltm_grid* g, uint64_t& off)
+{
+    auto place = [&](uint64_t& o, uint64_t bytes) { o = off; off = align256(off + bytes); };
+    place(t->off_ez_s, t->ez.start.size() * 4);
+    place(t->off_ez_w, t->ez.w.size() * 4);
+    place(t->off_ezt_s, t->ezt.start.size() * 4);
+    place(t->off_ezt_w, t->ezt.w.size() * 4);
+    place(t->off_ex_s, t->ex.start.size() * 4);
+    place(t->off_ex_w, t->ex.w.size() * 4);
+    place(t->off_ext_s, t->ext.start.size() * 4);
+    place(t->off_ext_w, t->ext.w.size() * 4);
+    place(t->off_r1, (uint64_t)t->nzr * g->ny * g->nx * 4);
+    place(t->off_xr, (uint64_t)t->nzr * g->ny * t->nxr * 4);
+}
+
 // The factorized plenoptic model (camera-model section, plenoptic camera):
 // slices -> array plane per angular cell, the rasterized aperture mask, then
 // each lenslet -> detector.  Array pixels: the detector's pixel pitch, k per
 // lenslet.  Tables hold the table entries with the slice thickness folded into
 // the s factor of stage 1 and the measurement normalization (the pixel
 // integral divided by dp^2 times the lenslet bounding square's solid angle
-// (2 r / D_d)^2, over V^d) into the s factor of stage 2.
+// (2 r / D_d)^2, over V^d) into the s factor of stage 2.  A posed camera
+// takes the transport grid of the rotated volume (anisotropic voxels).
+struct Pose {
+    bool rot;
+    double sa, sb;          // z shear (z += sa x) and x shear (x += sb z)
+    double hx, hy, hz;      // voxel sizes on the transport grid (s, t, depth)
+    int nxr, nzr;           // transport grid columns and slices
+};
+
 ltm_status create_plenoptic(const ltm_grid* g, const ltm_camera* c, uint32_t basis, double L,
-                            ltm_xport** out)
+                            const Pose& ps, ltm_xport** out)
 {
-    const int nx = (int)g->nx, ny = (int)g->ny, nz = (int)g->nz;
+    const int nx = ps.nxr, ny = (int)g->ny, nz = ps.nzr;
+    const double hx = ps.hx, hy = ps.hy, hz = ps.hz;
     const int nu = (int)c->det_nu, nv = (int)c->det_nv, mu = (int)c->mla_nu, mv = (int)c->mla_nv;
     const int ka = nu / mu;
     if (nv / mv != ka)
         return fail(LTM_ERR_UNSUPPORTED, "the factorized plenoptic transport needs square lenslets "
                                          "(det_nu / mla_nu == det_nv / mla_nv)");
     const int Ks = (int)c->rays_u, Kt = (int)c->rays_v;
-    const double dx = g->pitch_mm, dp = c->pixel_pitch_mm, P = ka * dp, da = dp;
+    const double dp = c->pixel_pitch_mm, P = ka * dp, da = dp;
     const double r = c->r_main_mm, d0s = 2.0 * r / Ks, d0t = 2.0 * r / Kt;
     const double Dm = c->d_mla_mm, Dd = c->d_mla_det_mm;
-    if (!(L - 0.5 * nz * dx > 0.0)) return fail(LTM_ERR_INVALID, "every slice must lie in front of the lens");
+    if (!(L - 0.5 * nz * hz > 0.0)) return fail(LTM_ERR_INVALID, "every slice must lie in front of the lens");
     const uint64_t m1 = (uint64_t)nz * Kt * nv * (uint64_t)nx;
     if (m1 > (1ull << 34) || (uint64_t)Ks * Kt * nv * (uint64_t)nu > (1ull << 34))
         return fail(LTM_ERR_INVALID, "intermediates larger than 2^34 values");
@@ -304,6 +346,10 @@ ltm_status create_plenoptic(const ltm_grid* g, const ltm_camera* c, uint32_t bas
     t->cam = *c;
     t->basis = basis;
     t->plen = true;
+    t->rot = ps.rot;
+    t->nxr = nx;
+    t->nyr = ny;
+    t->nzr = nz;
     t->kt = Kt;
     t->ks = Ks;
     t->na_u = nu;
@@ -340,19 +386,19 @@ ltm_status create_plenoptic(const ltm_grid* g, const ltm_camera* c, uint32_t bas
     // stage 1: per (slice, kt) t factor and per (slice, ks) s factor
     std::vector<Rows> bt1, bs1;
     for (int iz = 0; iz < nz; ++iz) {
-        const double z = L + (iz + 0.5 - 0.5 * nz) * dx;
+        const double z = L + (iz + 0.5 - 0.5 * nz) * hz;
         const Aff X0q = aff_inv(aff_mul(aff_T(z), aff_R(c->f_main_mm, 0.0)));
         const Aff Xaq = aff_mul(aff_inv(X0a), X0q);
         for (int kt = 0; kt < Kt; ++kt) {
             const Kernel1D k1 = kernel_affine((int)basis, Xaq, X0q, (kt + 0.5) * d0t - r, d0t, da);
             Rows rows(na_v);
-            for (int va = 0; va < na_v; ++va) factor_row(k1, (va + 0.5 - 0.5 * na_v) * da, dx, ny, 1.0, rows[va]);
+            for (int va = 0; va < na_v; ++va) factor_row(k1, (va + 0.5 - 0.5 * na_v) * da, hy, ny, 1.0, rows[va]);
             bt1.push_back(std::move(rows));
         }
         for (int ks = 0; ks < Ks; ++ks) {
             const Kernel1D k1 = kernel_affine((int)basis, Xaq, X0q, (ks + 0.5) * d0s - r, d0s, da);
             Rows rows(na_u);
-            for (int ua = 0; ua < na_u; ++ua) factor_row(k1, (ua + 0.5 - 0.5 * na_u) * da, dx, nx, dx, rows[ua]);
+            for (int ua = 0; ua < na_u; ++ua) factor_row(k1, (ua + 0.5 - 0.5 * na_u) * da, hx, nx, hz, rows[ua]);
             bs1.push_back(std::move(rows));
         }
     }
@@ -402,6 +448,10 @@ ltm_status create_plenoptic(const ltm_grid* g, const ltm_camera* c, uint32_t bas
     place(17, t->mask.size() * 4);
     place(18, m1 * 4 + (uint64_t)t->ncells * na_v * na_u * 4);      // M1, then FA
     place(19, (uint64_t)t->ncells * nv * na_u * 4);                 // M2
+    if (ps.rot) {
+        build_shears(t, g, ps.sa, ps.sb, hx, hz);
+        place_shears(t, g, off);
+    }
     t->ws_bytes = off;
     *out = t;
     clear_error();
@@ -443,10 +493,6 @@ ltm_status ltm_xport_create(const ltm_grid* g, const ltm_camera* c, uint32_t bas
             return fail(LTM_ERR_UNSUPPORTED, "the transport operator needs the lens on the camera axis through the grid centre");
     const double cphi = std::cos(phi), sphi = std::sin(phi);
     const bool rot = std::fabs(sphi) > 1e-15;
-    if (c->kind == LTM_PLENOPTIC) {
-        if (rot) return fail(LTM_ERR_UNSUPPORTED, "the factorized plenoptic transport needs a head-on camera");
-        return create_plenoptic(g, c, basis, L, out);
-    }
     const double sa = -sphi * cphi, sb = sphi / cphi;           // S_z: z += sa x, S_x: x += sb z
     const double d = g->pitch_mm;
     const double hx = rot ? d / cphi : d, hy = d, hz = rot ? d * cphi : d;
@@ -454,6 +500,10 @@ ltm_status ltm_xport_create(const ltm_grid* g, const ltm_camera* c, uint32_t bas
     if (rot) {
         nzr = (int)g->nz + 2 * (int)std::ceil(0.5 * std::fabs(sa) * g->nx * hx / hz) + 2;
         nxr = (int)g->nx + 2 * (int)std::ceil(0.5 * std::fabs(sb) * nzr * hz / hx) + 2;
+    }
+    if (c->kind == LTM_PLENOPTIC) {
+        const Pose ps{rot, sa, sb, hx, hy, hz, nxr, nzr};
+        return create_plenoptic(g, c, basis, L, ps, out);
     }
     if (!(L - 0.5 * nzr * hz > 0.0))
         return fail(LTM_ERR_INVALID, "every slice must lie in front of the lens");
@@ -519,20 +569,7 @@ ltm_status ltm_xport_create(const ltm_grid* g, const ltm_camera* c, uint32_t bas
     const int pairs = nz * Kt;
     transpose(t->cs, pairs, nx, t->cst);
     transpose(t->bt, pairs, ny, t->btt);
-    if (rot) {
-        // E^z per natural x column (shift sa * x, spread |sa| hx), then E^x
-        // per sheared z row (shift sb * z, spread |sb| hz)
-        const int nx1 = (int)g->nx, nz1 = (int)g->nz;
-        std::vector<Rows> ezp, exp_;
-        for (int x1 = 0; x1 < nx1; ++x1)
-            ezp.push_back(shear_rows(nzr, nz1, hz, sa * (x1 + 0.5 - 0.5 * nx1) * hx, std::fabs(sa) * hx));
-        for (int z = 0; z < nzr; ++z)
-            exp_.push_back(shear_rows(nxr, nx1, hx, sb * (z + 0.5 - 0.5 * nzr) * hz, std::fabs(sb) * hz));
-        pack(ezp, nzr, t->ez);
-        pack(exp_, nxr, t->ex);
-        transpose(t->ez, nx1, nz1, t->ezt);
-        transpose(t->ex, nzr, nx1, t->ext);
-    }
+    if (rot) build_shears(t, g, sa, sb, hx, hz);
     uint64_t off = 0;
     auto place = [&](uint64_t& o, uint64_t bytes) { o = off; off = align256(off + bytes); };
     place(t->off_bt_s, t->bt.start.size() * 4);
@@ -544,18 +581,7 @@ ltm_status ltm_xport_create(const ltm_grid* g, const ltm_camera* c, uint32_t bas
     place(t->off_btt_s, t->btt.start.size() * 4);
     place(t->off_btt_w, t->btt.w.size() * 4);
     place(t->off_mid, mid * 4);
-    if (rot) {
-        place(t->off_ez_s, t->ez.start.size() * 4);
-        place(t->off_ez_w, t->ez.w.size() * 4);
-        place(t->off_ezt_s, t->ezt.start.size() * 4);
-        place(t->off_ezt_w, t->ezt.w.size() * 4);
-        place(t->off_ex_s, t->ex.start.size() * 4);
-        place(t->off_ex_w, t->ex.w.size() * 4);
-        place(t->off_ext_s, t->ext.start.size() * 4);
-        place(t->off_ext_w, t->ext.w.size() * 4);
-        place(t->off_r1, (uint64_t)nzr * g->ny * g->nx * 4);
-        place(t->off_xr, (uint64_t)nzr * g->ny * nxr * 4);
-    }
+    if (rot) place_shears(t, g, off);
     t->ws_bytes = off;
     *out = t;
     clear_error();
@@ -619,6 +645,8 @@ ltm_status ltm_xport_bind_workspace(ltm_xport* t, void* ws, uint64_t bytes, void
         all.push_back({t->off_pl[16] + nc * 4, t->cell_kt.data(), nc * 4});
         all.push_back({t->off_pl[16] + 2 * nc * 4, t->cell_first.data(), nf * 4});
         all.push_back({t->off_pl[17], t->mask.data(), t->mask.size() * 4});
+        if (t->rot)
+            for (int i = 8; i < 16; ++i) all.push_back(ups[i]);   // the shear tables
     } else {
         all.assign(std::begin(ups), std::end(ups));
     }
@@ -691,9 +719,9 @@ ltm::ShearDev shear_of(const ltm_xport* t)
 ltm::PlenDev plen_of(const ltm_xport* t)
 {
     ltm::PlenDev d{};
-    d.nx = (int)t->grid.nx;
-    d.ny = (int)t->grid.ny;
-    d.nz = (int)t->grid.nz;
+    d.nx = t->nxr;
+    d.ny = t->nyr;
+    d.nz = t->nzr;
     d.na_u = t->na_u;
     d.na_v = t->na_v;
     d.nu = (int)t->cam.det_nu;
@@ -741,7 +769,11 @@ ltm_status ltm_xport_project(ltm_xport* t, const float* x, float* y, void* strea
     if (!t->bound) return fail(LTM_ERR_WORKSPACE, "transport operator has no bound workspace");
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
-    if (t->plen) {
+    if (t->plen && t->rot) {
+        const ltm::ShearDev r = shear_of(t);
+        e = launch_shear_forward(r, x, s);
+        if (e == hipSuccess) e = launch_plen_project(plen_of(t), r.xr, y, s);
+    } else if (t->plen) {
         e = launch_plen_project(plen_of(t), x, y, s);
     } else if (t->rot) {
         const ltm::ShearDev r = shear_of(t);
@@ -759,7 +791,11 @@ ltm_status ltm_xport_backproject(ltm_xport* t, const float* y, float* x, void* s
     if (!t->bound) return fail(LTM_ERR_WORKSPACE, "transport operator has no bound workspace");
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
-    if (t->plen) {
+    if (t->plen && t->rot) {
+        const ltm::ShearDev r = shear_of(t);
+        e = launch_plen_backproject(plen_of(t), y, r.xr, s);
+        if (e == hipSuccess) e = launch_shear_adjoint(r, x, s);
+    } else if (t->plen) {
         e = launch_plen_backproject(plen_of(t), y, x, s);
     } else if (t->rot) {
         const ltm::ShearDev r = shear_of(t);

@@ -431,8 +431,8 @@ def reg_grad_add(grid: dict, z: torch.Tensor, g: torch.Tensor, beta: float, psi_
 class Transport:
     """The paper's L2-projected light-field transport (Dirac or pillbox
     angular basis) for one single-lens camera at an azimuth pose, or the
-    factorized model of one head-on square-array plenoptic camera; see
-    ltm_xport_* in include/ltm.h.  Tables and the filtering intermediate live in a device
+    factorized model of one square-array plenoptic camera at an azimuth pose;
+    see ltm_xport_* in include/ltm.h.  Tables and the filtering intermediate live in a device
     workspace owned by this object."""
 
     def __init__(self, grid: dict, camera: dict, basis: int = BASIS_PILLBOX, device="cuda"):

@@ -176,8 +176,16 @@ def test_transport_operator_validation(L):
     b = (ctypes.c_uint32 * 4)()
     assert L.lib().ltm_xport_bands(h, b) == 0 and all(v >= 1 for v in b)
     L.lib().ltm_xport_destroy(h)
+    # posed plenoptic: the rotated grid's volumes join the workspace
+    for phi in (20.0, -45.0):
+        pp = W.plenoptic_camera(64, 4, (3, 3), 8, phi_deg=phi)
+        assert L.lib().ltm_xport_create(ctypes.byref(L.make_grid(g)), L.make_cameras([pp]), 1,
+                                        ctypes.byref(h)) == 0
+        m = ctypes.c_uint64()
+        assert L.lib().ltm_xport_workspace_bytes(h, ctypes.byref(m)) == 0 and m.value > n.value
+        L.lib().ltm_xport_destroy(h)
     cases = [(W.single_lens_camera(128, (4, 4), 8, phi_deg=50.0), L.LTM_ERR_UNSUPPORTED, "45 deg"),
-             (W.plenoptic_camera(64, 4, (2, 2), 8, phi_deg=20.0), L.LTM_ERR_UNSUPPORTED, "head-on"),
+             (W.plenoptic_camera(64, 4, (2, 2), 8, phi_deg=50.0), L.LTM_ERR_UNSUPPORTED, "45 deg"),
              (W.hex_plenoptic_camera(64, (4, 4)), L.LTM_ERR_UNSUPPORTED, "square-array"),
              (dict(W.plenoptic_camera(64, 4, (2, 2), 8), det_nv=32), L.LTM_ERR_UNSUPPORTED,
               "square lenslets"),
