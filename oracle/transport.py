@@ -316,6 +316,42 @@ def rotate_azimuth_adjoint(g: dict, xr, phi_deg: float):
     return out
 
 
+def quarter_turns(phi_deg: float):
+    """phi = 90 q + phi' with |phi'| <= 45 deg: the quarter turns q and phi'."""
+    q = int(round(phi_deg / 90.0))
+    return q, phi_deg - 90.0 * q
+
+
+def quarter_turn(g: dict, x, q: int):
+    """The volume a camera at phi sees as if it stood at phi - 90 q: the
+    value at p' is x(R(90 q) p'), R the rotation about y that maps camera
+    axes (e_s, e_t, e_z) to world axes.  An exact permutation of voxels (with
+    reversals); odd q swap the x and z extents.  Returns (x_q, g_q)."""
+    x = np.asarray(x, np.float64).reshape(g["nz"], g["ny"], g["nx"])
+    q %= 4
+    if q == 0:
+        return x.copy(), dict(g)
+    if q == 2:
+        return x[::-1, :, ::-1].copy(), dict(g)
+    # x_q[iz'][iy][ix']: q = 1 reads x[nz-1-ix'][iy][iz'], q = 3 reads x[ix'][iy][nx-1-iz']
+    t = np.transpose(x, (2, 1, 0))                       # t[ix][iy][iz] = x[iz][iy][ix]
+    xq = t[:, :, ::-1] if q == 1 else t[::-1, :, :]
+    return xq.copy(), dict(g, nx=g["nz"], nz=g["nx"])
+
+
+def quarter_turn_adjoint(g: dict, xq, q: int):
+    """The transpose (the inverse permutation) of ``quarter_turn``."""
+    q %= 4
+    gq = dict(g, nx=g["nz"], nz=g["nx"]) if q % 2 else dict(g)
+    xq = np.asarray(xq, np.float64).reshape(gq["nz"], gq["ny"], gq["nx"])
+    if q == 0:
+        return xq.copy()
+    if q == 2:
+        return xq[::-1, :, ::-1].copy()
+    t = xq[:, :, ::-1] if q == 1 else xq[::-1, :, :]     # back to t[ix][iy][iz]
+    return np.transpose(t, (2, 1, 0)).copy()
+
+
 def _camera_distance(cam: dict) -> float:
     L = np.asarray(cam["lens_center"], np.float64)
     ez = np.asarray(cam["axes"][6:9], np.float64)
@@ -328,10 +364,12 @@ def _camera_distance(cam: dict) -> float:
 
 def project_posed(g: dict, cam: dict, x, basis: int = PILLBOX) -> np.ndarray:
     """A x for a single-lens camera at azimuth phi: rotate the coefficients
-    into the camera's axes (scaling and two shears), then the head-on
-    transport on the rotated grid's anisotropic voxels."""
-    phi = cam["phi_deg"]
-    xr, R = rotate_azimuth(g, x, phi)
+    into the camera's axes (quarter turns, then the scaling and two shears of
+    the remaining |phi'| <= 45 deg), then the head-on transport on the
+    rotated grid's anisotropic voxels."""
+    q, phi = quarter_turns(cam["phi_deg"])
+    xq, gq = quarter_turn(g, x, q)
+    xr, R = rotate_azimuth(gq, xq, phi)
     head = dict(cam, axes=[1.0, 0, 0, 0, 1.0, 0, 0, 0, 1.0],
                 lens_center=[0.0, 0.0, -_camera_distance(cam)])
     gr = dict(nx=R["nx"], ny=R["ny"], nz=R["nz"], pitch=(R["hx"], R["hy"], R["hz"]))
@@ -339,13 +377,14 @@ def project_posed(g: dict, cam: dict, x, basis: int = PILLBOX) -> np.ndarray:
 
 
 def backproject_posed(g: dict, cam: dict, y, basis: int = PILLBOX) -> np.ndarray:
-    phi = cam["phi_deg"]
-    R = rotated_grid(g, phi)
+    q, phi = quarter_turns(cam["phi_deg"])
+    gq = dict(g, nx=g["nz"], nz=g["nx"]) if q % 2 else dict(g)
+    R = rotated_grid(gq, phi)
     head = dict(cam, axes=[1.0, 0, 0, 0, 1.0, 0, 0, 0, 1.0],
                 lens_center=[0.0, 0.0, -_camera_distance(cam)])
     gr = dict(nx=R["nx"], ny=R["ny"], nz=R["nz"], pitch=(R["hx"], R["hy"], R["hz"]))
     xr = backproject(gr, head, y, basis)
-    return rotate_azimuth_adjoint(g, xr, phi).reshape(-1)
+    return quarter_turn_adjoint(g, rotate_azimuth_adjoint(gq, xr, phi), q).reshape(-1)
 
 
 # --------------------------------------------------------------------------
@@ -474,17 +513,22 @@ def _head_on_view(cam: dict):
 
 def project_plenoptic_posed(g: dict, cam: dict, x, basis: int = PILLBOX, ka: int | None = None):
     """A x of the factorized plenoptic model for a square-array plenoptic
-    camera at azimuth phi (|phi| <= 45 deg): the coefficients rotated into
-    the camera's axes (scaling and two shears), then the head-on factorized
-    transport on the rotated grid's anisotropic voxels."""
-    xr, Rg = rotate_azimuth(g, x, cam["phi_deg"])
+    camera at azimuth phi: the coefficients rotated into the camera's axes
+    (quarter turns, then the scaling and two shears of the remaining
+    |phi'| <= 45 deg), then the head-on factorized transport on the rotated
+    grid's anisotropic voxels."""
+    q, phi = quarter_turns(cam["phi_deg"])
+    xq, gq = quarter_turn(g, x, q)
+    xr, Rg = rotate_azimuth(gq, xq, phi)
     gr = dict(nx=Rg["nx"], ny=Rg["ny"], nz=Rg["nz"], pitch=(Rg["hx"], Rg["hy"], Rg["hz"]))
     return project_plenoptic(gr, _head_on_view(cam), xr, basis, ka)
 
 
 def backproject_plenoptic_posed(g: dict, cam: dict, y, basis: int = PILLBOX, ka: int | None = None):
     """A^T y of ``project_plenoptic_posed``."""
-    Rg = rotated_grid(g, cam["phi_deg"])
+    q, phi = quarter_turns(cam["phi_deg"])
+    gq = dict(g, nx=g["nz"], nz=g["nx"]) if q % 2 else dict(g)
+    Rg = rotated_grid(gq, phi)
     gr = dict(nx=Rg["nx"], ny=Rg["ny"], nz=Rg["nz"], pitch=(Rg["hx"], Rg["hy"], Rg["hz"]))
     xr = backproject_plenoptic(gr, _head_on_view(cam), y, basis, ka)
-    return rotate_azimuth_adjoint(g, xr, cam["phi_deg"]).reshape(-1)
+    return quarter_turn_adjoint(g, rotate_azimuth_adjoint(gq, xr, phi), q).reshape(-1)
