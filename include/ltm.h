@@ -372,10 +372,15 @@ ltm_status ltm_nn_add(float* a, const float* b, uint64_t n, void* stream);
 /* ------------------------------------------------------------------------ */
 /* The paper's own discretization (light-field discretization, light
  * transport, object-model, camera-model and rotated-perspective sections;
- * Dirac and pillbox transport tables), for a single-lens camera at azimuth
- * phi about the grid's y axis (e_t = +y), |phi| <= 45 deg, with the lens on
- * the camera axis through the grid centre.  A posed camera first rotates the
- * volume into its axes as the paper does: with c = cos phi the voxels scale
+ * Dirac and pillbox transport tables), for a single-lens camera at any
+ * azimuth phi about the grid's y axis (e_t = +y), with the lens on the camera
+ * axis through the grid centre.  With phi = 90 q + phi', |phi'| <= 45 deg (q
+ * the nearest integer, half-way cases to even), the volume is first turned
+ * by q quarter turns about y, an exact permutation of voxels that swaps the
+ * x and z extents for odd q: the turned volume at p' is the volume at
+ * R(90 q) p', R the rotation from camera to world axes.  A posed camera then
+ * rotates the turned volume by phi' into its axes as the paper does, with
+ * phi' in place of phi below: with c = cos phi the voxels scale
  * to (pitch/c, pitch, pitch c) along (s, t, depth), then a z shear
  * (z += -sin(phi) c x) and an x shear (x += tan(phi) z) resample the
  * coefficients, each the L2 projection of the sheared boxes (a piecewise
@@ -412,7 +417,8 @@ ltm_status ltm_nn_add(float* a, const float* b, uint64_t n, void* stream);
  * bounding square.  Workspace: the tables plus three FP32 intermediates,
  * nz * rays_v * det_nv * nx (slices filtered along t), cells * det_nv *
  * det_nu (the masked array-plane light field), and the same again (after
- * the lenslet t stage), plus the two rotated volumes of a posed camera. */
+ * the lenslet t stage), plus the two rotated volumes of a posed camera and
+ * the turned volume when q != 0. */
 enum { LTM_BASIS_DIRAC = 0u, LTM_BASIS_PILLBOX = 1u };
 
 typedef struct ltm_xport ltm_xport;

@@ -19,7 +19,7 @@
 #include "ltm_xport.h"
 
 struct ltm_xport {
-    ltm_grid grid;
+    ltm_grid grid;                 // the grid after the quarter turns (natural when q = 0)
     ltm_camera cam;
     uint32_t basis;
     int kt;                        // angular rows (rays_v)
@@ -29,7 +29,11 @@ struct ltm_xport {
         std::vector<int32_t> start;   // pairs * rows
         std::vector<float> w;         // pairs * width * rows (weight-major)
     } bt, cs, cst, btt;
-    // posed cameras: rotation of the natural grid into the camera's axes
+    // posed cameras: q quarter turns of the volume about y (x and z extents
+    // swap for odd q), then the shear rotation of the remaining |phi'| <= 45 deg
+    int q = 0;                     // 0..3
+    int nx0 = 0, nz0 = 0;          // natural grid columns and slices
+    uint64_t off_turn = 0;         // the turned volume (when q != 0)
     bool rot = false;
     int nxr = 0, nyr = 0, nzr = 0;          // transport grid (rotated, or the natural one)
     Band ez, ezt, ex, ext;
@@ -308,6 +312,18 @@ void place_shears(ltm_xport* t, const ltm_grid* g, uint64_t& off)
     place(t->off_xr, (uint64_t)t->nzr * g->ny * t->nxr * 4);
 }
 
+// The quarter turns of a posed camera: the natural grid's extents and a
+// workspace place for the turned volume, after the operator's other places.
+void add_turn(ltm_xport* t, int q, const ltm_grid& gq)
+{
+    t->q = q;
+    t->nx0 = (int)((q & 1) ? gq.nz : gq.nx);
+    t->nz0 = (int)((q & 1) ? gq.nx : gq.nz);
+    if (q == 0) return;
+    t->off_turn = t->ws_bytes;
+    t->ws_bytes = align256(t->ws_bytes + (uint64_t)gq.nx * gq.ny * gq.nz * 4);
+}
+
 // The factorized plenoptic model (camera-model section, plenoptic camera):
 // slices -> array plane per angular cell, the rasterized aperture mask, then
 // each lenslet -> detector.  Array pixels: the detector's pixel pitch, k per
@@ -476,16 +492,20 @@ ltm_status ltm_xport_create(const ltm_grid* g, const ltm_camera* c, uint32_t bas
     if (st != LTM_OK) return st;
     if (c->kind != LTM_SINGLE_LENS && c->kind != LTM_PLENOPTIC)
         return fail(LTM_ERR_UNSUPPORTED, "the transport operator models single-lens and square-array plenoptic cameras");
-    // pose: azimuth phi about the grid's y axis, |phi| <= 45 deg, the lens on
-    // the camera axis through the grid centre
+    // pose: azimuth phi about the grid's y axis, the lens on the camera axis
+    // through the grid centre; phi = 90 q + phi' with |phi'| <= 45 deg
     const double* es = c->axes;
     const double* et = c->axes + 3;
     const double* ez = c->axes + 6;
     if (std::fabs(et[1] - 1.0) > 1e-12 || std::fabs(es[1]) > 1e-12 || std::fabs(ez[1]) > 1e-12)
         return fail(LTM_ERR_UNSUPPORTED, "the transport operator needs an azimuth pose (e_t = +y)");
-    const double phi = std::atan2(ez[0], ez[2]);
-    if (std::fabs(phi) > 0.25 * M_PI + 1e-12)
-        return fail(LTM_ERR_UNSUPPORTED, "the transport operator's shear rotation needs |phi| <= 45 deg");
+    const double phi0 = std::atan2(ez[0], ez[2]);
+    const int q = (int)std::nearbyint(phi0 / (0.5 * M_PI));      // half-way cases to even
+    const double phi = phi0 - 0.5 * M_PI * q;
+    // the volume turned by q quarter turns is what a camera at phi' sees
+    ltm_grid gq = *g;
+    if (q & 1) std::swap(gq.nx, gq.nz);
+    g = &gq;
     const double L = -(c->lens_center_mm[0] * ez[0] + c->lens_center_mm[1] * ez[1] +
                        c->lens_center_mm[2] * ez[2]);
     for (int a = 0; a < 3; ++a)
@@ -501,9 +521,12 @@ ltm_status ltm_xport_create(const ltm_grid* g, const ltm_camera* c, uint32_t bas
         nzr = (int)g->nz + 2 * (int)std::ceil(0.5 * std::fabs(sa) * g->nx * hx / hz) + 2;
         nxr = (int)g->nx + 2 * (int)std::ceil(0.5 * std::fabs(sb) * nzr * hz / hx) + 2;
     }
+    const int qm = ((q % 4) + 4) % 4;
     if (c->kind == LTM_PLENOPTIC) {
         const Pose ps{rot, sa, sb, hx, hy, hz, nxr, nzr};
-        return create_plenoptic(g, c, basis, L, ps, out);
+        st = create_plenoptic(g, c, basis, L, ps, out);
+        if (st == LTM_OK) add_turn(*out, qm, gq);
+        return st;
     }
     if (!(L - 0.5 * nzr * hz > 0.0))
         return fail(LTM_ERR_INVALID, "every slice must lie in front of the lens");
@@ -583,6 +606,7 @@ ltm_status ltm_xport_create(const ltm_grid* g, const ltm_camera* c, uint32_t bas
     place(t->off_mid, mid * 4);
     if (rot) place_shears(t, g, off);
     t->ws_bytes = off;
+    add_turn(t, qm, gq);
     *out = t;
     clear_error();
     return LTM_OK;
@@ -769,19 +793,19 @@ ltm_status ltm_xport_project(ltm_xport* t, const float* x, float* y, void* strea
     if (!t->bound) return fail(LTM_ERR_WORKSPACE, "transport operator has no bound workspace");
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
-    if (t->plen && t->rot) {
-        const ltm::ShearDev r = shear_of(t);
-        e = launch_shear_forward(r, x, s);
-        if (e == hipSuccess) e = launch_plen_project(plen_of(t), r.xr, y, s);
-    } else if (t->plen) {
-        e = launch_plen_project(plen_of(t), x, y, s);
-    } else if (t->rot) {
-        const ltm::ShearDev r = shear_of(t);
-        e = launch_shear_forward(r, x, s);
-        if (e == hipSuccess) e = launch_xport_project(dev_of(t), r.xr, y, s);
-    } else {
-        e = launch_xport_project(dev_of(t), x, y, s);
+    // quarter turns, then the shear rotation, then the head-on transport
+    if (t->q) {
+        float* xq = reinterpret_cast<float*>(t->ws + t->off_turn);
+        e = launch_turn(x, xq, t->nx0, t->nyr, t->nz0, t->q, s);
+        x = xq;
     }
+    if (e == hipSuccess && t->rot) {
+        const ltm::ShearDev r = shear_of(t);
+        e = launch_shear_forward(r, x, s);
+        x = r.xr;
+    }
+    if (e == hipSuccess)
+        e = t->plen ? launch_plen_project(plen_of(t), x, y, s) : launch_xport_project(dev_of(t), x, y, s);
     return e == hipSuccess ? LTM_OK : hip_fail(e, "transport project");
 }
 
@@ -790,20 +814,16 @@ ltm_status ltm_xport_backproject(ltm_xport* t, const float* y, float* x, void* s
     if (!t || !x || !y) return fail(LTM_ERR_INVALID, "null argument");
     if (!t->bound) return fail(LTM_ERR_WORKSPACE, "transport operator has no bound workspace");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = hipSuccess;
-    if (t->plen && t->rot) {
-        const ltm::ShearDev r = shear_of(t);
-        e = launch_plen_backproject(plen_of(t), y, r.xr, s);
-        if (e == hipSuccess) e = launch_shear_adjoint(r, x, s);
-    } else if (t->plen) {
-        e = launch_plen_backproject(plen_of(t), y, x, s);
-    } else if (t->rot) {
-        const ltm::ShearDev r = shear_of(t);
-        e = launch_xport_backproject(dev_of(t), y, r.xr, s);
-        if (e == hipSuccess) e = launch_shear_adjoint(r, x, s);
-    } else {
-        e = launch_xport_backproject(dev_of(t), y, x, s);
-    }
+    // the transposes in reverse order: transport, shears, quarter turns
+    float* xq = t->q ? reinterpret_cast<float*>(t->ws + t->off_turn) : x;
+    const ltm::ShearDev r = t->rot ? shear_of(t) : ltm::ShearDev{};
+    float* xt = t->rot ? r.xr : xq;
+    hipError_t e = t->plen ? launch_plen_backproject(plen_of(t), y, xt, s)
+                           : launch_xport_backproject(dev_of(t), y, xt, s);
+    if (e == hipSuccess && t->rot) e = launch_shear_adjoint(r, xq, s);
+    // the turn by -q on the turned grid is the inverse permutation
+    if (e == hipSuccess && t->q)
+        e = launch_turn(xq, x, (int)t->grid.nx, t->nyr, (int)t->grid.nz, (4 - t->q) % 4, s);
     return e == hipSuccess ? LTM_OK : hip_fail(e, "transport backproject");
 }
 

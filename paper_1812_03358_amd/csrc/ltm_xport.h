@@ -71,5 +71,8 @@ hipError_t launch_xport_project(const XportDev& d, const float* x, float* y, hip
 hipError_t launch_xport_backproject(const XportDev& d, const float* y, float* x, hipStream_t s);
 hipError_t launch_shear_forward(const ShearDev& r, const float* x, hipStream_t s);
 hipError_t launch_shear_adjoint(const ShearDev& r, float* x, hipStream_t s);
+// q quarter turns about y of a volume on the grid (nz, ny, nx): dst on the
+// turned grid (nx, ny, nz for odd q), dst(p') = src(R(90 q) p').
+hipError_t launch_turn(const float* src, float* dst, int nx, int ny, int nz, int q, hipStream_t s);
 
 }  // namespace ltm

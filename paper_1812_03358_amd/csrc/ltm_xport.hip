@@ -400,6 +400,52 @@ __global__ __launch_bounds__(kBlock) void k_shear_z_t(ShearDev r, float* __restr
     }
 }
 
+// ---------------------------------------------------------------- quarter turns
+// dst on the turned grid, dst(p') = src(R(90 q) p') with R the rotation about
+// y.  With the natural grid (nz, ny, nx): q = 1 reads src[nz-1-x'][y][z'],
+// q = 3 reads src[x'][y][nx-1-z'] (x and z extents swap), q = 2 reads
+// src[nz-1-z'][y][nx-1-x'].  Odd turns transpose each y plane through a
+// padded LDS tile so that reads and writes both run along rows.
+constexpr int kTurn = 32;
+
+__global__ __launch_bounds__(256) void k_turn_odd(const float* __restrict__ src, float* __restrict__ dst,
+                                                  int nx, int ny, int nz, int q)
+{
+    __shared__ float tile[kTurn][kTurn + 1];
+    const int nxq = nz, nzq = nx;                       // turned grid
+    const int b0 = blockIdx.x * kTurn, a0 = blockIdx.y * kTurn, y = blockIdx.z;
+    const int tx = threadIdx.x & (kTurn - 1), ty = threadIdx.x / kTurn;
+    // tile[b][a] = dst[a0 + a][b0 + b]: lanes walk a, a source row
+    for (int k = ty; k < kTurn; k += 256 / kTurn) {
+        const int a = a0 + tx, b = b0 + k;
+        if (a < nzq && b < nxq) {
+            const int zs = q == 1 ? nz - 1 - b : b;
+            const int xs = q == 1 ? a : nx - 1 - a;
+            tile[k][tx] = src[((size_t)zs * ny + y) * nx + xs];
+        }
+    }
+    __syncthreads();
+    // lanes walk b, a destination row
+    for (int k = ty; k < kTurn; k += 256 / kTurn) {
+        const int a = a0 + k, b = b0 + tx;
+        if (a < nzq && b < nxq) dst[((size_t)a * ny + y) * nxq + b] = tile[tx][k];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_turn_half(const float* __restrict__ src, float* __restrict__ dst,
+                                                      int nx, int ny, int nz)
+{
+    const size_t total = (size_t)nz * ny * nx;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * kBlock) {
+        const int x = (int)(i % nx);
+        const size_t r = i / nx;
+        const int y = (int)(r % ny);
+        const int z = (int)(r / ny);
+        dst[i] = src[((size_t)(nz - 1 - z) * ny + y) * nx + (nx - 1 - x)];
+    }
+}
+
 unsigned grid_for(size_t n)
 {
     const size_t b = (n + kBlock - 1) / kBlock;
@@ -440,6 +486,22 @@ hipError_t launch_xport_project(const XportDev& d, const float* x, float* y, hip
     case 3: hipLaunchKernelGGL(k_major_fwd_w<3>, g, b, 0, s, d, y); break;
     case 4: hipLaunchKernelGGL(k_major_fwd_w<4>, g, b, 0, s, d, y); break;
     default: hipLaunchKernelGGL(k_major_fwd, g, b, 0, s, d, y); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_turn(const float* src, float* dst, int nx, int ny, int nz, int q, hipStream_t s)
+{
+    q = ((q % 4) + 4) % 4;
+    if (q == 0)
+        return hipMemcpyAsync(dst, src, (size_t)nx * ny * nz * sizeof(float), hipMemcpyDeviceToDevice, s);
+    if (q == 2) {
+        hipLaunchKernelGGL(k_turn_half, dim3(grid_for((size_t)nx * ny * nz)), dim3(kBlock), 0, s,
+                           src, dst, nx, ny, nz);
+    } else {
+        if (ny > 65535 || (nx + kTurn - 1) / kTurn > 65535) return hipErrorInvalidValue;
+        const dim3 g((unsigned)((nz + kTurn - 1) / kTurn), (unsigned)((nx + kTurn - 1) / kTurn), (unsigned)ny);
+        hipLaunchKernelGGL(k_turn_odd, g, dim3(256), 0, s, src, dst, nx, ny, nz, q);
     }
     return hipGetLastError();
 }

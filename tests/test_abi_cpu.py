@@ -160,11 +160,20 @@ def test_transport_operator_validation(L):
         assert L.lib().ltm_xport_project(h, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == \
             L.LTM_ERR_WORKSPACE
         L.lib().ltm_xport_destroy(h)
-    for phi in (20.0, -45.0):                            # posed: the shear rotation
-        cam = W.single_lens_camera(128, (4, 4), 8, phi_deg=phi)
-        assert L.lib().ltm_xport_create(ctypes.byref(L.make_grid(g)), L.make_cameras([cam]), 1,
-                                        ctypes.byref(h)) == 0
+    def ws_of(cam, grid=g):
+        assert L.lib().ltm_xport_create(ctypes.byref(L.make_grid(grid)), L.make_cameras([cam]), 1,
+                                        ctypes.byref(h)) == 0, L.lib().ltm_last_error()
+        n = ctypes.c_uint64()
+        assert L.lib().ltm_xport_workspace_bytes(h, ctypes.byref(n)) == 0
         L.lib().ltm_xport_destroy(h)
+        return n.value
+
+    # posed: quarter turns, then the shear rotation of the rest
+    ws0 = ws_of(W.single_lens_camera(128, (4, 4), 8))
+    for phi in (20.0, -45.0, 50.0, 135.0, 180.0, -100.0):
+        assert ws_of(W.single_lens_camera(128, (4, 4), 8, phi_deg=phi)) > ws0
+    # a quarter turn alone adds one turned volume (24^3 floats, 256-byte aligned)
+    assert ws_of(W.single_lens_camera(128, (4, 4), 8, phi_deg=90.0)) == ws0 + 4 * 24 ** 3
     # head-on square-array plenoptic: the factorized model, three intermediates
     pl = W.plenoptic_camera(64, 4, (3, 3), 8)
     assert L.lib().ltm_xport_create(ctypes.byref(L.make_grid(g)), L.make_cameras([pl]), 1,
@@ -177,15 +186,17 @@ def test_transport_operator_validation(L):
     assert L.lib().ltm_xport_bands(h, b) == 0 and all(v >= 1 for v in b)
     L.lib().ltm_xport_destroy(h)
     # posed plenoptic: the rotated grid's volumes join the workspace
-    for phi in (20.0, -45.0):
+    for phi in (20.0, -45.0, 100.0, -170.0):
         pp = W.plenoptic_camera(64, 4, (3, 3), 8, phi_deg=phi)
         assert L.lib().ltm_xport_create(ctypes.byref(L.make_grid(g)), L.make_cameras([pp]), 1,
                                         ctypes.byref(h)) == 0
         m = ctypes.c_uint64()
         assert L.lib().ltm_xport_workspace_bytes(h, ctypes.byref(m)) == 0 and m.value > n.value
         L.lib().ltm_xport_destroy(h)
-    cases = [(W.single_lens_camera(128, (4, 4), 8, phi_deg=50.0), L.LTM_ERR_UNSUPPORTED, "45 deg"),
-             (W.plenoptic_camera(64, 4, (2, 2), 8, phi_deg=50.0), L.LTM_ERR_UNSUPPORTED, "45 deg"),
+    import math
+    a = math.radians(10.0)                               # a roll about the optical axis
+    rolled = dict(ok, axes=[math.cos(a), math.sin(a), 0, -math.sin(a), math.cos(a), 0, 0, 0, 1])
+    cases = [(rolled, L.LTM_ERR_UNSUPPORTED, "azimuth pose"),
              (W.hex_plenoptic_camera(64, (4, 4)), L.LTM_ERR_UNSUPPORTED, "square-array"),
              (dict(W.plenoptic_camera(64, 4, (2, 2), 8), det_nv=32), L.LTM_ERR_UNSUPPORTED,
               "square lenslets"),

@@ -286,3 +286,99 @@ def test_posed_plenoptic_transport_full_size_dot(ltm):
         float(Ax.norm()) * float(y.double().norm()))
     print(f"posed plenoptic transport 128^3 x 1024^2 at 30 deg: dot {dot:.2e}", flush=True)
     assert float(Ax.norm()) > 0 and dot < 1e-9
+
+
+# ----------------------------------------------- quarter turns: every azimuth
+@pytest.mark.parametrize("phi,basis", [(90.0, 1), (120.0, 0), (-100.0, 1), (180.0, 1), (-160.0, 0)])
+def test_posed_transport_beyond_45_deg_matches_oracle(ltm, phi, basis):
+    # q quarter turns (an exact permutation, x and z extents swapped for odd
+    # q), then the shears of the remaining |phi'| <= 45 deg
+    g = W.grid((18, 14, 16), 1.0)
+    cam = W.single_lens_camera(160, (4, 4), 8, phi_deg=phi)
+    x = W.flame(18, seed=6)[:16, :14, :18]
+    y = W.uniform_random(160 * 160, seed=7)
+    op = ltm.Transport(g, cam, basis)
+    Ax = op.project(_dev(x)).cpu().numpy()
+    Aty = op.backproject(_dev(y)).cpu().numpy()
+    ref_Ax = OT.project_posed(g, cam, x, basis)
+    ref_Aty = OT.backproject_posed(g, cam, y, basis)
+    x64, y64 = x.astype(np.float64).reshape(-1), y.astype(np.float64)
+    dot = abs(Ax.astype(np.float64) @ y64 - x64 @ Aty.astype(np.float64)) / (
+        np.linalg.norm(Ax) * np.linalg.norm(y64))
+    e1, e2 = rel_l2(Ax, ref_Ax), rel_l2(Aty, ref_Aty)
+    print(f"posed transport phi={phi} basis={basis}: A {e1:.2e} A^T {e2:.2e} dot {dot:.2e}", flush=True)
+    assert np.linalg.norm(ref_Ax) > 0
+    assert e1 < 1e-5 and e2 < 1e-5
+    # the small-grid posed bar; at whole quarter turns the operator is the
+    # head-on one on the turned grid bit for bit (checked below), and its
+    # dot here is a rounding statistic of that grid's few terms
+    assert dot < 1e-8
+
+
+@pytest.mark.parametrize("phi,q", [(90.0, 1), (-90.0, -1), (180.0, 2)])
+def test_quarter_turn_is_exact_on_the_gpu(ltm, phi, q):
+    # a camera at 90 q deg sees the turned volume head-on: the same tables
+    # and kernels, so A x and A^T y agree bit for bit with the head-on
+    # operator on the turned grid
+    g = W.grid((20, 12, 14), 1.0)
+    cam = W.single_lens_camera(128, (4, 4), 8, phi_deg=phi)
+    x = W.flame(20, seed=15)[:14, :12, :20]
+    y = W.uniform_random(128 * 128, seed=16)
+    xq, gq = OT.quarter_turn(g, x, q)
+    head = ltm.Transport(gq, W.single_lens_camera(128, (4, 4), 8), 1)
+    op = ltm.Transport(g, cam, 1)
+    Ax = op.project(_dev(x)).cpu().numpy()
+    Aty = op.backproject(_dev(y)).cpu().numpy()
+    ref_Ax = head.project(_dev(xq)).cpu().numpy()
+    ref_Aty = OT.quarter_turn_adjoint(g, head.backproject(_dev(y)).cpu().numpy(), q).reshape(-1)
+    assert np.linalg.norm(ref_Ax) > 0
+    assert np.array_equal(Ax, ref_Ax)
+    assert np.array_equal(Aty, ref_Aty.astype(np.float32))
+
+
+@pytest.mark.parametrize("basis", [0, 1])
+@pytest.mark.parametrize("phi,dims,pitch,det,mla,rays", [(100.0, (16, 16, 16), 6.0, 64, 8, (8, 8)),
+                                                         (-135.0, (20, 14, 12), 4.0, 96, 8, (4, 6)),
+                                                         (90.0, (12, 12, 9), 8.0, 128, 16, (5, 5))])
+def test_posed_plenoptic_beyond_45_deg_matches_oracle(ltm, basis, phi, dims, pitch, det, mla, rays):
+    g = W.grid(dims, pitch)
+    cam = W.plenoptic_camera(det, mla, rays, 8, phi_deg=phi)
+    x = W.flame(max(dims), seed=11)[:dims[2], :dims[1], :dims[0]]
+    y = W.uniform_random(det * det, seed=12)
+    op = ltm.Transport(g, cam, basis)
+    Ax = op.project(_dev(x)).cpu().numpy()
+    Aty = op.backproject(_dev(y)).cpu().numpy()
+    ref_Ax = OT.project_plenoptic_posed(g, cam, x, basis)
+    ref_Aty = OT.backproject_plenoptic_posed(g, cam, y, basis)
+    e1, e2 = rel_l2(Ax, ref_Ax), rel_l2(Aty, ref_Aty)
+    dot = _plen_dot(Ax, y, x, Aty)
+    print(f"posed plenoptic transport phi={phi} basis={basis} dims={dims}: A {e1:.2e} A^T {e2:.2e} "
+          f"dot {dot:.2e}", flush=True)
+    assert np.linalg.norm(ref_Ax) > 0 and np.linalg.norm(ref_Aty) > 0
+    assert e1 < 1e-5 and e2 < 1e-5
+    assert dot < 3e-8
+
+
+def test_posed_transport_beyond_45_deg_full_size(ltm):
+    # 128^3 x 1024^2 plenoptic at 120 deg (dot identity), and the single-lens
+    # 1024^2 camera at 150 deg against the ray-driven operator on 100^3
+    g = W.grid(128, 1.25)
+    op = ltm.Transport(g, W.plenoptic_camera(1024, 64, (4, 4), 8, phi_deg=120.0), 1)
+    x = torch.from_numpy(W.flame(128, seed=13).reshape(-1)).cuda()
+    y = torch.from_numpy(W.uniform_random(1024 * 1024, seed=14)).cuda()
+    Ax = op.project(x).double()
+    Aty = op.backproject(y).double()
+    dot = abs(float(Ax @ y.double()) - float(x.double() @ Aty)) / (
+        float(Ax.norm()) * float(y.double().norm()))
+    print(f"posed plenoptic transport 128^3 x 1024^2 at 120 deg: dot {dot:.2e}", flush=True)
+    assert float(Ax.norm()) > 0 and dot < 1e-9
+    g = W.grid(100, 1.0)
+    cam = W.single_lens_camera(1024, (8, 8), 200, phi_deg=150.0)
+    xs = W.flame(100, seed=5)
+    A1 = ltm.Transport(g, cam, 1).project(_dev(xs)).cpu().numpy()
+    Ar = ltm.Plan(g, [cam]).project(_dev(xs)).cpu().numpy()
+    d = rel_l2(A1, Ar)
+    print(f"posed transport 1024^2 150 deg: vs ray-driven {d:.3f}, sums {A1.sum() / Ar.sum():.5f}",
+          flush=True)
+    assert abs(A1.sum() / Ar.sum() - 1.0) < 2e-3
+    assert d < 0.1
