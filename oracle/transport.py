@@ -317,7 +317,9 @@ def rotate_azimuth_adjoint(g: dict, xr, phi_deg: float):
 
 
 def quarter_turns(phi_deg: float):
-    """phi = 90 q + phi' with |phi'| <= 45 deg: the quarter turns q and phi'."""
+    """phi = 90 q + phi' with |phi'| <= 45 deg: the quarter turns q and phi'
+    (rotated-perspective section: a rotation over 45 deg is a permutation,
+    whole quarter turns, composed with a smaller rotation)."""
     q = int(round(phi_deg / 90.0))
     return q, phi_deg - 90.0 * q
 
