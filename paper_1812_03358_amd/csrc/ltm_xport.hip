@@ -24,26 +24,59 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kRowsPerThread = 1;   // forward major pass: detector rows per thread
 
-// M[p][v][ix] = sum_k bt.w[p][k][v] * x[iz][start + k][ix],  p = iz * kt + kt_i
+// Row kernels: grid y walks the output rows (the row's coordinates, band
+// start and weights are then uniform across the workgroup and decoded once),
+// threads the row's columns.
+struct RowGrid {
+    dim3 g, b;
+};
+
+RowGrid row_grid(size_t rows, int cols)
+{
+    const int bs = cols >= kBlock ? kBlock : ((cols + 63) / 64) * 64;
+    const unsigned gx = (unsigned)((cols + bs - 1) / bs);
+    const unsigned gy = (unsigned)(rows < 65535 ? (rows ? rows : 1) : 65535);
+    return {dim3(gx, gy), dim3((unsigned)bs)};
+}
+
+constexpr int kMinorRows = 8;   // minor passes: output rows per thread
+
+// mid[p][v][ix] = sum_k bt.w[p][k][v] * x[iz][start + k][ix], p = (iz, kt):
+// a thread takes column ix of kMinorRows consecutive rows v of one pair, so
+// that the rows' table and volume loads are in flight together; each output
+// is still summed over k in order.
 __global__ __launch_bounds__(kBlock) void k_minor_fwd(XportDev d, const float* __restrict__ x)
 {
-    const size_t total = (size_t)d.nz * d.kt * d.nv * d.nx;
-    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
-         i += (size_t)gridDim.x * kBlock) {
-        const int ix = (int)(i % d.nx);
-        const size_t r = i / d.nx;
-        const int v = (int)(r % d.nv);
-        const size_t p = r / d.nv;
+    constexpr int R = kMinorRows;
+    const int ix = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ix >= d.nx) return;
+    const int vb = (d.nv + R - 1) / R;
+    const size_t groups = (size_t)d.nz * d.kt * vb;
+    for (size_t g = blockIdx.y; g < groups; g += gridDim.y) {
+        const int v0 = (int)(g % vb) * R;
+        const size_t p = g / vb;
         const size_t iz = p / d.kt;
-        const int st = d.bt.start[p * d.nv + v];
-        const float* w = d.bt.w + p * d.bt.width * (size_t)d.nv + v;
         const float* xs = x + iz * d.ny * (size_t)d.nx + ix;
-        float acc = 0.0f;
-        for (int k = 0; k < d.bt.width; ++k) {
-            const int iy = st + k;
-            if (iy < d.ny) acc = fmaf(w[(size_t)k * d.nv], xs[(size_t)iy * d.nx], acc);
+        const int32_t* st = d.bt.start + p * d.nv;
+        const float* w = d.bt.w + p * d.bt.width * (size_t)d.nv;
+        int s0[R];
+        float acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            s0[r] = st[min(v0 + r, d.nv - 1)];
+            acc[r] = 0.0f;
         }
-        d.mid[i] = acc;
+        for (int k = 0; k < d.bt.width; ++k) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int iy = s0[r] + k;
+                if (iy < d.ny)
+                    acc[r] = fmaf(w[(size_t)k * d.nv + min(v0 + r, d.nv - 1)], xs[(size_t)iy * d.nx], acc[r]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (v0 + r < d.nv) d.mid[(p * d.nv + v0 + r) * d.nx + ix] = acc[r];
     }
 }
 
@@ -319,11 +352,11 @@ __global__ __launch_bounds__(kBlock) void k_minor_adj(XportDev d, float* __restr
 // r1[z][y][x1] = sum_k ez.w[x1][k][z] * x[start + k][y][x1]
 __global__ __launch_bounds__(kBlock) void k_shear_z(ShearDev r, const float* __restrict__ x)
 {
-    const size_t total = (size_t)r.nz * r.ny * r.nx1;
-    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
-         i += (size_t)gridDim.x * kBlock) {
-        const int x1 = (int)(i % r.nx1);
-        const size_t q = i / r.nx1;
+    const int x1 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x1 >= r.nx1) return;
+    const size_t rows = (size_t)r.nz * r.ny;
+    for (size_t q = blockIdx.y; q < rows; q += gridDim.y) {
+        const size_t i = q * r.nx1 + x1;
         const int y = (int)(q % r.ny);
         const int z = (int)(q / r.ny);
         const int st = r.ez.start[(size_t)x1 * r.nz + z];
@@ -340,11 +373,11 @@ __global__ __launch_bounds__(kBlock) void k_shear_z(ShearDev r, const float* __r
 // xr[z][y][x] = sum_k ex.w[z][k][x] * r1[z][y][start + k]
 __global__ __launch_bounds__(kBlock) void k_shear_x(ShearDev r)
 {
-    const size_t total = (size_t)r.nz * r.ny * r.nx;
-    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
-         i += (size_t)gridDim.x * kBlock) {
-        const int x = (int)(i % r.nx);
-        const size_t q = i / r.nx;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= r.nx) return;
+    const size_t rows = (size_t)r.nz * r.ny;
+    for (size_t q = blockIdx.y; q < rows; q += gridDim.y) {
+        const size_t i = q * r.nx + x;
         const int z = (int)(q / r.ny);
         const int st = r.ex.start[(size_t)z * r.nx + x];
         const float* w = r.ex.w + (size_t)z * r.ex.width * r.nx + x;
@@ -361,11 +394,11 @@ __global__ __launch_bounds__(kBlock) void k_shear_x(ShearDev r)
 // r1[z][y][x1] = sum_k ext.w[z][k][x1] * xr[z][y][start + k]
 __global__ __launch_bounds__(kBlock) void k_shear_x_t(ShearDev r)
 {
-    const size_t total = (size_t)r.nz * r.ny * r.nx1;
-    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
-         i += (size_t)gridDim.x * kBlock) {
-        const int x1 = (int)(i % r.nx1);
-        const size_t q = i / r.nx1;
+    const int x1 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x1 >= r.nx1) return;
+    const size_t rows = (size_t)r.nz * r.ny;
+    for (size_t q = blockIdx.y; q < rows; q += gridDim.y) {
+        const size_t i = q * r.nx1 + x1;
         const int z = (int)(q / r.ny);
         const int st = r.ext.start[(size_t)z * r.nx1 + x1];
         const float* w = r.ext.w + (size_t)z * r.ext.width * r.nx1 + x1;
@@ -382,11 +415,11 @@ __global__ __launch_bounds__(kBlock) void k_shear_x_t(ShearDev r)
 // x[z1][y][x1] = sum_k ezt.w[x1][k][z1] * r1[start + k][y][x1]
 __global__ __launch_bounds__(kBlock) void k_shear_z_t(ShearDev r, float* __restrict__ x)
 {
-    const size_t total = (size_t)r.nz1 * r.ny * r.nx1;
-    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
-         i += (size_t)gridDim.x * kBlock) {
-        const int x1 = (int)(i % r.nx1);
-        const size_t q = i / r.nx1;
+    const int x1 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x1 >= r.nx1) return;
+    const size_t rows = (size_t)r.nz1 * r.ny;
+    for (size_t q = blockIdx.y; q < rows; q += gridDim.y) {
+        const size_t i = q * r.nx1 + x1;
         const int y = (int)(q % r.ny);
         const int z1 = (int)(q / r.ny);
         const int st = r.ezt.start[(size_t)x1 * r.nz1 + z1];
@@ -456,8 +489,10 @@ unsigned grid_for(size_t n)
 
 hipError_t launch_xport_project(const XportDev& d, const float* x, float* y, hipStream_t s)
 {
-    const size_t nm = (size_t)d.nz * d.kt * d.nv * d.nx;
-    hipLaunchKernelGGL(k_minor_fwd, dim3(grid_for(nm)), dim3(kBlock), 0, s, d, x);
+    {
+        const RowGrid rg = row_grid((size_t)d.nz * d.kt * ((d.nv + kMinorRows - 1) / kMinorRows), d.nx);
+        hipLaunchKernelGGL(k_minor_fwd, rg.g, rg.b, 0, s, d, x);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // LDS-staged pass for band widths up to 4 while 4 rows of one pair fit 64 KiB
@@ -508,19 +543,31 @@ hipError_t launch_turn(const float* src, float* dst, int nx, int ny, int nz, int
 
 hipError_t launch_shear_forward(const ShearDev& r, const float* x, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_shear_z, dim3(grid_for((size_t)r.nz * r.ny * r.nx1)), dim3(kBlock), 0, s, r, x);
+    {
+        const RowGrid rg = row_grid((size_t)r.nz * r.ny, r.nx1);
+        hipLaunchKernelGGL(k_shear_z, rg.g, rg.b, 0, s, r, x);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_shear_x, dim3(grid_for((size_t)r.nz * r.ny * r.nx)), dim3(kBlock), 0, s, r);
+    {
+        const RowGrid rg = row_grid((size_t)r.nz * r.ny, r.nx);
+        hipLaunchKernelGGL(k_shear_x, rg.g, rg.b, 0, s, r);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_shear_adjoint(const ShearDev& r, float* x, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_shear_x_t, dim3(grid_for((size_t)r.nz * r.ny * r.nx1)), dim3(kBlock), 0, s, r);
+    {
+        const RowGrid rg = row_grid((size_t)r.nz * r.ny, r.nx1);
+        hipLaunchKernelGGL(k_shear_x_t, rg.g, rg.b, 0, s, r);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_shear_z_t, dim3(grid_for((size_t)r.nz1 * r.ny * r.nx1)), dim3(kBlock), 0, s, r, x);
+    {
+        const RowGrid rg = row_grid((size_t)r.nz1 * r.ny, r.nx1);
+        hipLaunchKernelGGL(k_shear_z_t, rg.g, rg.b, 0, s, r, x);
+    }
     return hipGetLastError();
 }
 
@@ -546,8 +593,7 @@ hipError_t launch_xport_backproject(const XportDev& d, const float* y, float* x,
         hipLaunchKernelGGL(k_major_adj, g, b, 0, s, d, y);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t nx = (size_t)d.nz * d.ny * d.nx;
-    hipLaunchKernelGGL(k_minor_adj, dim3(grid_for(nx)), dim3(kBlock), 0, s, d, x);
+    hipLaunchKernelGGL(k_minor_adj, dim3(grid_for((size_t)d.nz * d.ny * d.nx)), dim3(kBlock), 0, s, d, x);
     return hipGetLastError();
 }
 
@@ -709,62 +755,148 @@ __global__ __launch_bounds__(kBlockF) void k_pl_major1_lds(PlenDev d, int zc, in
 // M2[c][vd][ua] = sum_k bt2[kt_c][vd][k] FA[c][st + k][ua]
 __global__ __launch_bounds__(kBlock) void k_pl_minor2(PlenDev d)
 {
-    const size_t total = (size_t)d.cells * d.nv * d.na_u;
-    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
-         i += (size_t)gridDim.x * kBlock) {
-        const int ua = (int)(i % d.na_u);
-        const size_t q = i / d.na_u;
-        const int vd = (int)(q % d.nv);
-        const int c = (int)(q / d.nv);
+    constexpr int R = kMinorRows;
+    const int ua = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ua >= d.na_u) return;
+    const int vb = (d.nv + R - 1) / R;
+    const size_t groups = (size_t)d.cells * vb;
+    for (size_t g = blockIdx.y; g < groups; g += gridDim.y) {
+        const int v0 = (int)(g % vb) * R;
+        const int c = (int)(g / vb);
         const float* col = d.fa + (size_t)c * d.na_v * d.na_u + ua;
-        d.m2[i] = (float)band_dot(d.bt2, (size_t)d.cell_kt[c], vd, col, d.na_u, d.na_v);
+        const size_t tab = (size_t)d.cell_kt[c];
+        const int32_t* st = d.bt2.start + tab * d.bt2.rows;
+        const float* w = d.bt2.w + tab * d.bt2.width * (size_t)d.bt2.rows;
+        int s0[R];
+        double acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            s0[r] = st[min(v0 + r, d.nv - 1)];
+            acc[r] = 0.0;
+        }
+        for (int k = 0; k < d.bt2.width; ++k) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int va = s0[r] + k;
+                if (va < d.na_v)
+                    acc[r] += (double)(w[(size_t)k * d.bt2.rows + min(v0 + r, d.nv - 1)] *
+                                       col[(size_t)va * d.na_u]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (v0 + r < d.nv) d.m2[((size_t)c * d.nv + v0 + r) * d.na_u + ua] = (float)acc[r];
     }
 }
 
 // y[vd][ud] = sum_c sum_k bs2[ks_c][ud][k] M2[c][vd][st + k]
+// (kMinorRows detector rows per thread share the column's band; each output
+// sums a cell's band in order, then the cells in order)
 __global__ __launch_bounds__(kBlock) void k_pl_major2(PlenDev d, float* __restrict__ y)
 {
-    const size_t total = (size_t)d.nv * d.nu;
-    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
-         i += (size_t)gridDim.x * kBlock) {
-        const int ud = (int)(i % d.nu);
-        const int vd = (int)(i / d.nu);
-        double acc = 0.0;
+    constexpr int R = kMinorRows;
+    const int ud = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ud >= d.nu) return;
+    const int vb = (d.nv + R - 1) / R;
+    for (int g = blockIdx.y; g < vb; g += gridDim.y) {
+        const int v0 = g * R;
+        double acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = 0.0;
         for (int c = 0; c < d.cells; ++c) {
-            const float* row = d.m2 + ((size_t)c * d.nv + vd) * d.na_u;
-            acc += band_dot(d.bs2, (size_t)d.cell_ks[c], ud, row, 1, d.na_u);
+            const size_t tab = (size_t)d.cell_ks[c];
+            const int st = d.bs2.start[tab * d.bs2.rows + ud];
+            const float* w = d.bs2.w + tab * d.bs2.width * (size_t)d.bs2.rows + ud;
+            const float* m = d.m2 + (size_t)c * d.nv * d.na_u;
+            double part[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) part[r] = 0.0;
+            for (int k = 0; k < d.bs2.width; ++k) {
+                const int col = st + k;
+                if (col >= d.na_u) break;
+                const float wk = w[(size_t)k * d.bs2.rows];
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    part[r] += (double)(wk * m[(size_t)min(v0 + r, d.nv - 1) * d.na_u + col]);
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] += part[r];
         }
-        y[i] = (float)acc;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (v0 + r < d.nv) y[(size_t)(v0 + r) * d.nu + ud] = (float)acc[r];
     }
 }
 
 // M2[c][vd][ua] = sum_k bs2t[ks_c][ua][k] y[vd][st + k]
+// (kMinorRows detector rows per thread share the array column's band)
 __global__ __launch_bounds__(kBlock) void k_pl_major2_t(PlenDev d, const float* __restrict__ y)
 {
-    const size_t total = (size_t)d.cells * d.nv * d.na_u;
-    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
-         i += (size_t)gridDim.x * kBlock) {
-        const int ua = (int)(i % d.na_u);
-        const size_t q = i / d.na_u;
-        const int vd = (int)(q % d.nv);
-        const int c = (int)(q / d.nv);
-        d.m2[i] = (float)band_dot(d.bs2t, (size_t)d.cell_ks[c], ua, y + (size_t)vd * d.nu, 1, d.nu);
+    constexpr int R = kMinorRows;
+    const int ua = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ua >= d.na_u) return;
+    const int vb = (d.nv + R - 1) / R;
+    const size_t groups = (size_t)d.cells * vb;
+    for (size_t g = blockIdx.y; g < groups; g += gridDim.y) {
+        const int v0 = (int)(g % vb) * R;
+        const int c = (int)(g / vb);
+        const size_t tab = (size_t)d.cell_ks[c];
+        const int st = d.bs2t.start[tab * d.bs2t.rows + ua];
+        const float* w = d.bs2t.w + tab * d.bs2t.width * (size_t)d.bs2t.rows + ua;
+        double acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = 0.0;
+        for (int k = 0; k < d.bs2t.width; ++k) {
+            const int col = st + k;
+            if (col >= d.nu) break;
+            const float wk = w[(size_t)k * d.bs2t.rows];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                acc[r] += (double)(wk * y[(size_t)min(v0 + r, d.nv - 1) * d.nu + col]);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (v0 + r < d.nv) d.m2[((size_t)c * d.nv + v0 + r) * d.na_u + ua] = (float)acc[r];
     }
 }
 
 // FA[c][va][ua] = mask[va][ua] * sum_k bt2t[kt_c][va][k] M2[c][st + k][ua]
 __global__ __launch_bounds__(kBlock) void k_pl_minor2_t(PlenDev d)
 {
-    const size_t total = (size_t)d.cells * d.na_v * d.na_u;
-    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
-         i += (size_t)gridDim.x * kBlock) {
-        const int ua = (int)(i % d.na_u);
-        const size_t q = i / d.na_u;
-        const int va = (int)(q % d.na_v);
-        const int c = (int)(q / d.na_v);
+    constexpr int R = kMinorRows;
+    const int ua = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ua >= d.na_u) return;
+    const int vb = (d.na_v + R - 1) / R;
+    const size_t groups = (size_t)d.cells * vb;
+    for (size_t g = blockIdx.y; g < groups; g += gridDim.y) {
+        const int v0 = (int)(g % vb) * R;
+        const int c = (int)(g / vb);
         const float* col = d.m2 + (size_t)c * d.nv * d.na_u + ua;
-        d.fa[i] = (float)band_dot(d.bt2t, (size_t)d.cell_kt[c], va, col, d.na_u, d.nv) *
-                  d.mask[(size_t)va * d.na_u + ua];
+        const size_t tab = (size_t)d.cell_kt[c];
+        const int32_t* st = d.bt2t.start + tab * d.bt2t.rows;
+        const float* w = d.bt2t.w + tab * d.bt2t.width * (size_t)d.bt2t.rows;
+        int s0[R];
+        double acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            s0[r] = st[min(v0 + r, d.na_v - 1)];
+            acc[r] = 0.0;
+        }
+        for (int k = 0; k < d.bt2t.width; ++k) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int vd = s0[r] + k;
+                if (vd < d.nv)
+                    acc[r] += (double)(w[(size_t)k * d.bt2t.rows + min(v0 + r, d.na_v - 1)] *
+                                       col[(size_t)vd * d.na_u]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (v0 + r < d.na_v) {
+                const size_t i = ((size_t)c * d.na_v + v0 + r) * d.na_u + ua;
+                d.fa[i] = (float)acc[r] * d.mask[(size_t)(v0 + r) * d.na_u + ua];
+            }
     }
 }
 
@@ -970,24 +1102,38 @@ hipError_t launch_plen_project(const PlenDev& p, const float* x, float* y, hipSt
     d.nx = p.nx; d.ny = p.ny; d.nz = p.nz; d.nu = p.na_u; d.nv = p.na_v; d.kt = p.kt;
     d.bt = p.bt1;
     d.mid = p.m1;
-    const size_t nm = (size_t)p.nz * p.kt * p.na_v * p.nx;
-    hipLaunchKernelGGL(k_minor_fwd, dim3(grid_for(nm)), dim3(kBlock), 0, s, d, x);
+    {
+        const RowGrid rg = row_grid((size_t)d.nz * d.kt * ((d.nv + kMinorRows - 1) / kMinorRows), d.nx);
+        hipLaunchKernelGGL(k_minor_fwd, rg.g, rg.b, 0, s, d, x);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     launch_major1(p, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pl_minor2, dim3(grid_for((size_t)p.cells * p.nv * p.na_u)), dim3(kBlock), 0, s, p);
+    {
+        const RowGrid rg = row_grid((size_t)p.cells * ((p.nv + kMinorRows - 1) / kMinorRows), p.na_u);
+        hipLaunchKernelGGL(k_pl_minor2, rg.g, rg.b, 0, s, p);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pl_major2, dim3(grid_for((size_t)p.nv * p.nu)), dim3(kBlock), 0, s, p, y);
+    {
+        const RowGrid rg = row_grid((size_t)((p.nv + kMinorRows - 1) / kMinorRows), p.nu);
+        hipLaunchKernelGGL(k_pl_major2, rg.g, rg.b, 0, s, p, y);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_plen_backproject(const PlenDev& p, const float* y, float* x, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pl_major2_t, dim3(grid_for((size_t)p.cells * p.nv * p.na_u)), dim3(kBlock), 0, s, p, y);
+    {
+        const RowGrid rg = row_grid((size_t)p.cells * ((p.nv + kMinorRows - 1) / kMinorRows), p.na_u);
+        hipLaunchKernelGGL(k_pl_major2_t, rg.g, rg.b, 0, s, p, y);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pl_minor2_t, dim3(grid_for((size_t)p.cells * p.na_v * p.na_u)), dim3(kBlock), 0, s, p);
+    {
+        const RowGrid rg = row_grid((size_t)p.cells * ((p.na_v + kMinorRows - 1) / kMinorRows), p.na_u);
+        hipLaunchKernelGGL(k_pl_minor2_t, rg.g, rg.b, 0, s, p);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     launch_major1_t(p, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
