@@ -500,7 +500,10 @@ ltm_status ltm_xport_create(const ltm_grid* g, const ltm_camera* c, uint32_t bas
     if (std::fabs(et[1] - 1.0) > 1e-12 || std::fabs(es[1]) > 1e-12 || std::fabs(ez[1]) > 1e-12)
         return fail(LTM_ERR_UNSUPPORTED, "the transport operator needs an azimuth pose (e_t = +y)");
     const double phi0 = std::atan2(ez[0], ez[2]);
-    const int q = (int)std::nearbyint(phi0 / (0.5 * M_PI));      // half-way cases to even
+    // nearest q; the azimuth read back from the axes carries rounding, so
+    // half-way cases within 1e-9 of a quarter are taken to even exactly
+    const double tq = phi0 / (0.5 * M_PI), fq = std::floor(tq);
+    const int q = std::fabs(tq - fq - 0.5) < 1e-9 ? (int)fq + ((int)fq & 1) : (int)std::nearbyint(tq);
     const double phi = phi0 - 0.5 * M_PI * q;
     // the volume turned by q quarter turns is what a camera at phi' sees
     ltm_grid gq = *g;
