@@ -385,7 +385,10 @@ ltm_status ltm_nn_add(float* a, const float* b, uint64_t n, void* stream);
  * (z += -sin(phi) c x) and an x shear (x += tan(phi) z) resample the
  * coefficients, each the L2 projection of the sheared boxes (a piecewise
  * quadratic kernel); the rotated grid grows to nz' = nz + 2 ceil(|sin c| nx
- * / (2 c^2)) + 2 slices and nx' = nx + 2 ceil(|tan| nz' c^2 / 2) + 2 columns.
+ * / (2 c^2)) + 2 slices and to nx' = nx + 2 k + 2 columns, the least k whose
+ * outermost column centre lies at least dx + |tan| dz / 2 beyond the volume's
+ * rotated image (a column holding only zeros is left out; dx, dz the rotated
+ * voxel sizes), and never more than nx + 2 ceil(|tan| nz' c^2 / 2) + 2.
  * The (rotated) volume is collapsed into its slices; slice iz at camera
  * depth z = distance + (iz + 1/2 - nz'/2) dz radiates the light field
  * dz * x[iz] for every angular cell.  The angular plane is the main

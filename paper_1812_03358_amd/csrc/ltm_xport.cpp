@@ -523,6 +523,19 @@ ltm_status ltm_xport_create(const ltm_grid* g, const ltm_camera* c, uint32_t bas
     if (rot) {
         nzr = (int)g->nz + 2 * (int)std::ceil(0.5 * std::fabs(sa) * g->nx * hx / hz) + 2;
         nxr = (int)g->nx + 2 * (int)std::ceil(0.5 * std::fabs(sb) * nzr * hz / hx) + 2;
+        // The x shear of the whole z-sheared box is wider than the image of the
+        // volume itself, a rotated rectangle: a column x1 (centre c1) is nonzero
+        // after the z shear only within |z - sa c1| < (nz hz + hz + |sa| hx) / 2,
+        // and (1 + sa sb) = cos^2 phi, so after the x shear every nonzero cell
+        // centre lies within |x| <= m.  Cells beyond that only ever hold zeros;
+        // the grid keeps the parity of nx (the same cell centres) and the
+        // outermost centre at least hx + |sb| hz / 2 beyond m.
+        const double ua = std::fabs(sa), ub = std::fabs(sb);
+        const double m = (0.5 * g->nx * hx - 0.5 * hx) * (1.0 - ua * ub) +
+                         ub * (0.5 * g->nz * hz + 0.5 * hz + 0.5 * ua * hx);
+        const double need = 2.0 * (m + hx + 0.5 * ub * hz) / hx + 1.0;
+        const int k = std::max(0, (int)std::ceil(0.5 * (need - (double)g->nx - 2.0)));
+        nxr = std::min(nxr, (int)g->nx + 2 * k + 2);
     }
     const int qm = ((q % 4) + 4) % 4;
     if (c->kind == LTM_PLENOPTIC) {
