@@ -386,7 +386,7 @@ def run_transport(args):
     from paper_1812_03358_amd import ltm, workloads as W
 
     g = W.grid(100, 1.0)
-    cam = W.single_lens_camera(1024, (8, 8), 1)
+    cam = W.single_lens_camera(1024, (8, 8), 1, phi_deg=args.phi)
     x = torch.from_numpy(W.flame(100, 5).reshape(-1)).cuda()
     t0 = time.perf_counter()
     op = ltm.Transport(g, cam, ltm.BASIS_PILLBOX)
@@ -419,8 +419,9 @@ def run_transport(args):
     nbytes = 2 * mid + 4 * (100 ** 3 + 1024 ** 2)
     out = base_record(args, 1000.0 / ms, ms,
                       "transport_100: paper's L2-projected light-field transport, pillbox basis, "
-                      "single-lens 1024^2 head-on, 100^3 flame at 1 mm, 8x8 angular cells; one A x + "
-                      "one A^T y per step", {"bands": op.bands(), "table_build_s": round(t_tables, 3)})
+                      f"single-lens 1024^2 {pose_text(args.phi)}, 100^3 flame at 1 mm, 8x8 angular "
+                      "cells; one A x + one A^T y per step",
+                      {"bands": op.bands(), "table_build_s": round(t_tables, 3), "phi_deg": args.phi})
     out["metric"] = "transport A x + A^T y pairs/s"
     out["unit"] = "pairs/s"
     gbs = 2 * nbytes / (ms * 1e-3) / 1e9
@@ -429,7 +430,7 @@ def run_transport(args):
     out["ms_project"] = round(f_ms, 4)
     out["ms_backproject"] = round(a_ms, 4)
     out["wall_s_timed"] = round(t_wall, 3)
-    if args.no_study:
+    if args.no_study or args.phi:
         return out
     # angular discretization study (no timing claims: each K builds its tables)
     ref_op = ltm.Transport(g, W.single_lens_camera(1024, (64, 64), 1), ltm.BASIS_DIRAC)
@@ -458,6 +459,13 @@ def run_transport(args):
     return out
 
 
+def pose_text(phi):
+    """The camera pose in a workload name; a posed camera's roofline bytes
+    stay those of the head-on operator (the rotated grid's intermediates and
+    the shear passes are extra work, not counted as algorithmic)."""
+    return "head-on" if not phi else f"at azimuth {phi:g} deg (roofline bytes of the head-on operator)"
+
+
 def run_plenoptic_transport(args):
     """The paper's factorized plenoptic transport (slices onto the lenslet
     array plane per angular cell, the aperture mask, each lenslet onto the
@@ -471,7 +479,7 @@ def run_plenoptic_transport(args):
 
     n, K = 128, 4
     g = W.grid(n, 1.25)
-    cam = W.plenoptic_camera(1024, 64, (K, K), 1)
+    cam = W.plenoptic_camera(1024, 64, (K, K), 1, phi_deg=args.phi)
     x = torch.from_numpy(W.flame(n, 2).reshape(-1)).cuda()
     t0 = time.perf_counter()
     op = ltm.Transport(g, cam, ltm.BASIS_PILLBOX)
@@ -504,14 +512,15 @@ def run_plenoptic_transport(args):
                 for i in range(K) for j in range(K))
     inter = n * K * 1024 * n + 2 * cells * 1024 * 1024
     nbytes = 4 * (n ** 3 + 1024 ** 2) + 2 * 4 * inter
-    ray = ltm.Plan(g, [W.plenoptic_camera(1024, 64, (8, 8), 256)])
+    ray = ltm.Plan(g, [W.plenoptic_camera(1024, 64, (8, 8), 256, phi_deg=args.phi)])
     yr = ray.project(x).double()
     nsd = float(torch.linalg.norm(y.double() - yr) / torch.linalg.norm(yr))
     out = base_record(args, 1000.0 / ms, ms,
                       "plenoptic_transport_128: paper's factorized plenoptic transport, pillbox "
-                      "basis, 1024^2 behind 64^2 lenslets head-on, 128^3 flame at 1.25 mm, 4x4 "
-                      "angular cells; one A x + one A^T y per step",
-                      {"bands": op.bands(), "table_build_s": round(t_tables, 3), "cells": cells})
+                      f"basis, 1024^2 behind 64^2 lenslets {pose_text(args.phi)}, 128^3 flame at "
+                      "1.25 mm, 4x4 angular cells; one A x + one A^T y per step",
+                      {"bands": op.bands(), "table_build_s": round(t_tables, 3), "cells": cells,
+                       "phi_deg": args.phi})
     out["metric"] = "transport A x + A^T y pairs/s"
     out["unit"] = "pairs/s"
     gbs = 2 * nbytes / (ms * 1e-3) / 1e9
@@ -676,6 +685,8 @@ def main():
     ap.add_argument("--max-iter", type=int, default=4000)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--no-study", action="store_true", help="transport_100: skip the angular study")
+    ap.add_argument("--phi", type=float, default=0.0,
+                    help="transport workloads: camera azimuth in degrees (posed transport)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
