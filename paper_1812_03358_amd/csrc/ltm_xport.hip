@@ -323,9 +323,12 @@ __global__ __launch_bounds__(kBlock) void k_major_adj(XportDev d, const float* _
     }
 }
 
-// x[iz][iy][ix] = sum_kt sum_k btt.w[p][k][iy] * M[p][start + k][ix]
+// x[iz][iy][ix] = sum_kt sum_k btt.w[p][k][iy] * M[p][start + k][ix]:
+// angular rows four at a time, each with its own FP64 partial sum, so that
+// their table and intermediate loads are in flight together.
 __global__ __launch_bounds__(kBlock) void k_minor_adj(XportDev d, float* __restrict__ x)
 {
+    constexpr int G = 4;
     const size_t total = (size_t)d.nz * d.ny * d.nx;
     for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
          i += (size_t)gridDim.x * kBlock) {
@@ -334,15 +337,29 @@ __global__ __launch_bounds__(kBlock) void k_minor_adj(XportDev d, float* __restr
         const int iy = (int)(r % d.ny);
         const size_t iz = r / d.ny;
         double acc = 0.0;
-        for (int kt = 0; kt < d.kt; ++kt) {
-            const size_t p = iz * d.kt + kt;
-            const int st = d.btt.start[p * d.ny + iy];
-            const float* w = d.btt.w + p * d.btt.width * (size_t)d.ny + iy;
-            const float* m = d.mid + p * d.nv * (size_t)d.nx + ix;
-            for (int k = 0; k < d.btt.width; ++k) {
-                const int v = st + k;
-                if (v < d.nv) acc += (double)(w[(size_t)k * d.ny] * m[(size_t)v * d.nx]);
+        for (int kt0 = 0; kt0 < d.kt; kt0 += G) {
+            int st[G];
+            const float* w[G];
+            const float* m[G];
+            double part[G];
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                // rows past the last repeat it with no terms (st = nv)
+                const bool live = kt0 + j < d.kt;
+                const size_t p = iz * d.kt + (live ? kt0 + j : d.kt - 1);
+                st[j] = live ? d.btt.start[p * d.ny + iy] : d.nv;
+                w[j] = d.btt.w + p * d.btt.width * (size_t)d.ny + iy;
+                m[j] = d.mid + p * d.nv * (size_t)d.nx + ix;
+                part[j] = 0.0;
             }
+            for (int k = 0; k < d.btt.width; ++k) {
+#pragma unroll
+                for (int j = 0; j < G; ++j) {
+                    const int v = st[j] + k;
+                    if (v < d.nv) part[j] += (double)(w[j][(size_t)k * d.ny] * m[j][(size_t)v * d.nx]);
+                }
+            }
+            acc += (part[0] + part[1]) + (part[2] + part[3]);
         }
         x[i] = (float)acc;
     }
