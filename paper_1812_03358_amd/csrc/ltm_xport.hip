@@ -7,10 +7,11 @@
 // where Cs(iz,kt) is the sum of the s factors of the row's unmasked cells
 // (the cells of one angular row share their t factor).  The adjoint runs the
 // transposed tables in the opposite order.  Every output has one writer
-// (no atomics): the minor passes write one intermediate value per thread and
-// the major passes accumulate a whole output in FP64 registers.
+// (no atomics): a minor-pass thread writes its own intermediate values and a
+// major-pass thread accumulates whole outputs in FP64 registers.
 //
-// A posed camera wraps these passes in the rotation's z and x shears; the
+// A posed camera wraps these passes in quarter turns of the volume and the
+// rotation's z and x shears; the
 // factorized plenoptic model chains two such separable stages (slices onto
 // the lenslet-array plane, the mask, each lenslet onto the detector).
 #include <algorithm>
