@@ -544,10 +544,13 @@ __device__ __forceinline__ void scatter_lds_window(const March& mr, int m0, int 
     const float qb0 = c == 2 ? mr.qs[1] : mr.qs[2], db = c == 2 ? mr.st[1] : mr.st[2];
     const float qc0 = c == 0 ? mr.qs[0] : (c == 1 ? mr.qs[1] : mr.qs[2]);
     const float dc = c == 0 ? mr.st[0] : (c == 1 ? mr.st[1] : mr.st[2]);
-    const float fsa = (float)sa, fsb = (float)sb, fsc = (float)sc;
+    const float fsa = (float)sa, fsb = (float)sb, fsc = (float)sc, nbase = -b.base;
     const int cnt = m1 - m0;
     int m = m0;
     if (skew) m += (int)(((threadIdx.x & 63) * (unsigned)cnt) >> 6);
+    // the sample index counts in FP32 (exact below 2^24) and wraps at m1
+    float fm = (float)m;
+    const float fm0 = (float)m0, fm1 = (float)m1;
     int cur = -1;
     float lo[4] = {0.f, 0.f, 0.f, 0.f}, hi[4] = {0.f, 0.f, 0.f, 0.f};
     auto flush4 = [&](int i, const float (&p)[4]) {
@@ -558,12 +561,11 @@ __device__ __forceinline__ void scatter_lds_window(const March& mr, int m0, int 
         atomicAdd(q + sa + sb, (T)p[3]);
     };
     for (int k = 0; k < cnt; ++k) {
-        const float fm = (float)m;
         const float qa = fmaf(fm, da, qa0), qb = fmaf(fm, db, qb0), qc = fmaf(fm, dc, qc0);
         const float ca = floorf(qa), cb = floorf(qb), cc = floorf(qc);
         const float fa = qa - ca, fb = qb - cb, fc = qc - cc;
         // the cell's LDS index: exact integer arithmetic in FP32 (brick indices < 2^24)
-        const float fi = fmaf(cc, fsc, fmaf(cb, fsb, ca * fsa)) - b.base;
+        const float fi = fmaf(cc, fsc, fmaf(cb, fsb, fmaf(ca, fsa, nbase)));
         const int i0 = (int)clampf(fi, 0.0f, maxi);
         if (i0 != cur) {
             const bool up = i0 == cur + sc, down = i0 == cur - sc;
@@ -587,8 +589,8 @@ __device__ __forceinline__ void scatter_lds_window(const March& mr, int m0, int 
             lo[j] = fmaf(vl, w[j], lo[j]);
             hi[j] = fmaf(vh, w[j], hi[j]);
         }
-        ++m;
-        m = m == m1 ? m0 : m;
+        fm += 1.0f;
+        fm = fm == fm1 ? fm0 : fm;
     }
     if (cur >= 0) {
         flush4(cur, lo);
