@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LTM_ABI_VERSION 2u
+#define LTM_ABI_VERSION 3u
 
 typedef enum ltm_status {
     LTM_OK = 0,
@@ -192,7 +192,9 @@ ltm_status ltm_project(ltm_plan* plan, const float* x, float* y, void* stream);
 
 /* x = A^T y with the same samples and weights as ltm_project (the adjoint
  * the paper's adjoint-operations section requires).  y: M floats,
- * x: N floats (zeroed, then accumulated with FP32 atomics). */
+ * x: N floats (overwritten).  Each sample's eight weighted values are
+ * rounded to FP32 and summed into an FP64 accumulator in the plan's
+ * workspace, which is rounded to FP32 once at the end. */
 ltm_status ltm_backproject(ltm_plan* plan, const float* y, float* x, void* stream);
 
 /* ---------------------------------------------------------------------- */
@@ -216,6 +218,11 @@ typedef struct ltm_solver_params {
     uint32_t n_subsets;         /* > 1: iteration n uses angular-sample subset n mod n_subsets
                                    (view-subset acceleration); the majorizer uses all samples */
     double beta, delta, nu, c_r;
+    /* Stop rule of ltm_solver_solve (the algorithm table's loop runs for N_iter
+     * iterations; a residual target ends it earlier): */
+    double rho_target;          /* stop once rho(x) <= rho_target; 0 runs max_iter iterations */
+    uint32_t max_iter;          /* N_iter: at most this many iterations per solve (>= 1) */
+    uint32_t check_every;       /* iterations between residual checks, one host sync each (>= 1) */
 } ltm_solver_params;
 
 typedef struct ltm_solver ltm_solver;
@@ -235,8 +242,34 @@ void ltm_solver_destroy(ltm_solver* solver);
  * t = 1, gains reset. */
 ltm_status ltm_solver_reset(ltm_solver* solver, const float* x0, void* stream);
 
+/* Restart from a candidate start x0 (N floats on the device, e.g. a learned
+ * estimate of the volume), judged by the plain solver.  x0 is scaled by the
+ * least-squares factor of its image, alpha = <A x0, y>_W / ||A x0||_W^2 (camera
+ * 1 only when gains are estimated, since the other cameras' gains absorb any
+ * scale), costing one projection.  At that scale rho(alpha x0)^2 = 1 - cos^2 of
+ * the angle between A x0 and y (gains off), below rho(0) = 1 whenever the two
+ * correlate positively.  The start is rejected -- the solver restarts from
+ * x = 0 instead -- when x0 holds a non-finite value, when alpha is not finite
+ * and positive (no positive correlation, or A x0 = 0), or when rho(alpha x0)
+ * is not below 1.  Outputs (host, any may be NULL): alpha, rho(alpha x0) (1
+ * when rejected) and accepted (1 or 0).
+ * Synchronizes the stream.  x0 is only read. */
+ltm_status ltm_solver_reset_warm(ltm_solver* solver, const float* x0, double* alpha, double* rho,
+                                 uint32_t* accepted, void* stream);
+
 /* Run n_iter iterations.  Asynchronous; no host synchronization. */
 ltm_status ltm_solver_step(ltm_solver* solver, uint32_t n_iter, void* stream);
+
+/* Run the algorithm from the current state until the stop rule of the
+ * parameters: every check_every iterations the monitored residual (at the
+ * extrapolated point) is read; once it is at or below rho_target the residual
+ * of x itself is computed (one extra projection) and the solve stops when that
+ * too is at or below the target.  Otherwise it stops after max_iter
+ * iterations, reporting the residual of x.  Outputs (host): iterations run in
+ * this call, converged (1 or 0) and rho(x).  Synchronizes once per check.
+ * Returns LTM_ERR_NUMERIC as soon as a residual is not finite. */
+ltm_status ltm_solver_solve(ltm_solver* solver, uint32_t* iterations, uint32_t* converged,
+                            double* rho, void* stream);
 
 /* Copy the current iterate x (N floats) into `x`. */
 ltm_status ltm_solver_get_x(const ltm_solver* solver, float* x, void* stream);
@@ -276,8 +309,12 @@ ltm_status ltm_reg_grad_add(const ltm_grid* grid, uint32_t psi_kind, double beta
  * uneven frames share the GPU without a launch per camera.  The sweep
  * allocates nothing, never synchronizes with the host and records no memset,
  * so it can be captured in a hipGraph (ltm_batch_graph_capture) and
- * replayed.  The plans' tilings and workspaces must not change while the
- * batch is used. */
+ * replayed.  A batch records each member plan's tables, tilings, view
+ * subset and workspace when it is created and bound: after any of them
+ * changes (ltm_plan_set_tiling, ltm_plan_bind_workspace,
+ * ltm_plan_set_ray_subset to another subset), ltm_batch_bind and every
+ * launch entry point, graph launch included, return LTM_ERR_WORKSPACE
+ * without launching; create the batch again. */
 typedef struct ltm_batch ltm_batch;
 
 ltm_status ltm_batch_create(ltm_plan* const* plans, uint32_t n_plans, ltm_batch** out);

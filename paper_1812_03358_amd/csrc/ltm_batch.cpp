@@ -31,6 +31,10 @@ struct ltm_batch {
     uint64_t cams_off[2] = {0, 0}, counter_off = 0, ws_bytes = 0;
     char* ws = nullptr;
     bool bound = false;
+    // member plans' generations and view subsets when the work lists were
+    // built (create) and when the tables were recorded (bind)
+    std::vector<uint64_t> gen_create, gen_bind;
+    std::vector<std::pair<uint32_t, uint32_t>> sub_bind;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -44,6 +48,22 @@ void release_graph(ltm_batch* b)
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
+}
+
+// LTM_OK while every member plan still has the tables, tilings, workspace
+// and view subset the batch recorded at bind time.
+ltm_status check_current(const ltm_batch* b)
+{
+    if (!b || !b->bound) return fail(LTM_ERR_WORKSPACE, "batch not bound");
+    for (size_t k = 0; k < b->plans.size(); ++k) {
+        const ltm_plan* p = b->plans[k];
+        if (!p->bound || p->generation != b->gen_bind[k] || p->sub_n != b->sub_bind[k].first ||
+            p->sub_i != b->sub_bind[k].second)
+            return fail(LTM_ERR_WORKSPACE, "plan " + std::to_string(k) +
+                                               " changed (tiling, workspace or view subset) since the "
+                                               "batch was bound; create the batch again");
+    }
+    return LTM_OK;
 }
 
 ltm_status run_dir(ltm_batch* b, int d, hipStream_t s)
@@ -97,6 +117,7 @@ ltm_status ltm_batch_create(ltm_plan* const* plans, uint32_t n_plans, ltm_batch*
             return fail(LTM_ERR_WORKSPACE, "plan " + std::to_string(i) + " is null or unbound");
         }
         b->plans.push_back(plans[i]);
+        b->gen_create.push_back(plans[i]->generation);
         for (size_t c = 0; c < plans[i]->cams.size(); ++c) b->pcs.push_back({(int)i, (int)c});
     }
     if (b->pcs.size() >= (1u << (32 - kTileBits))) {
@@ -161,7 +182,14 @@ ltm_status ltm_batch_bind(ltm_batch* b, void* ws, uint64_t bytes, const float* c
     if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(LTM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
     for (size_t k = 0; k < b->plans.size(); ++k)
         if (!x_in[k] || !y[k] || !x_out[k]) return fail(LTM_ERR_INVALID, "null buffer for plan " + std::to_string(k));
+    // the work lists and LDS sizes were built from the plans at creation
+    for (size_t k = 0; k < b->plans.size(); ++k)
+        if (!b->plans[k]->bound || b->plans[k]->generation != b->gen_create[k])
+            return fail(LTM_ERR_WORKSPACE, "plan " + std::to_string(k) +
+                                               " changed (tiling or workspace) since the batch was "
+                                               "created; create the batch again");
     release_graph(b);
+    b->bound = false;
     b->ws = static_cast<char*>(ws);
     int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -189,6 +217,12 @@ ltm_status ltm_batch_bind(ltm_batch* b, void* ws, uint64_t bytes, const float* c
     }
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "batch upload");
+    b->gen_bind.clear();
+    b->sub_bind.clear();
+    for (auto* p : b->plans) {
+        b->gen_bind.push_back(p->generation);
+        b->sub_bind.push_back({p->sub_n, p->sub_i});
+    }
     b->bound = true;
     clear_error();
     return LTM_OK;
@@ -196,13 +230,15 @@ ltm_status ltm_batch_bind(ltm_batch* b, void* ws, uint64_t bytes, const float* c
 
 ltm_status ltm_batch_project(ltm_batch* b, void* stream)
 {
-    if (!b || !b->bound) return fail(LTM_ERR_WORKSPACE, "batch not bound");
+    ltm_status st = check_current(b);
+    if (st != LTM_OK) return st;
     return run_dir(b, LTM_FORWARD, static_cast<hipStream_t>(stream));
 }
 
 ltm_status ltm_batch_backproject(ltm_batch* b, void* stream)
 {
-    if (!b || !b->bound) return fail(LTM_ERR_WORKSPACE, "batch not bound");
+    ltm_status st = check_current(b);
+    if (st != LTM_OK) return st;
     return run_dir(b, LTM_ADJOINT, static_cast<hipStream_t>(stream));
 }
 
@@ -215,7 +251,8 @@ ltm_status ltm_batch_sweep(ltm_batch* b, void* stream)
 
 ltm_status ltm_batch_graph_capture(ltm_batch* b, void* stream)
 {
-    if (!b || !b->bound) return fail(LTM_ERR_WORKSPACE, "batch not bound");
+    ltm_status cur = check_current(b);
+    if (cur != LTM_OK) return cur;
     if (!stream) return fail(LTM_ERR_INVALID, "graph capture needs a non-null stream");
     hipStream_t s = static_cast<hipStream_t>(stream);
     release_graph(b);
@@ -241,6 +278,8 @@ ltm_status ltm_batch_graph_capture(ltm_batch* b, void* stream)
 ltm_status ltm_batch_graph_launch(ltm_batch* b, void* stream)
 {
     if (!b || !b->exec) return fail(LTM_ERR_INVALID, "no captured graph");
+    ltm_status cur = check_current(b);
+    if (cur != LTM_OK) return cur;
     hipError_t e = hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "graph launch");
     return LTM_OK;

@@ -123,6 +123,9 @@ struct ltm_plan {
     uint32_t sub_n = 1, sub_i = 0;   // current angular-sample subset
     char* ws = nullptr;
     bool bound = false;
+    // bumped whenever the tables a launch reads may change (tiling, workspace
+    // binding), so that batches built on the plan can detect it
+    uint64_t generation = 0;
 };
 
 namespace ltm {

@@ -1,6 +1,7 @@
 // Host side of the camera operator: descriptor validation, the FP64 ray
 // constants of each camera, tilings, workspace layout and the C ABI of
 // project / backproject.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -138,8 +139,14 @@ uint64_t rays_per_pixel(const ltm_camera& c)
     return c.kind == LTM_PLENOPTIC_HEX ? 9 * R : R;
 }
 
-ltm_status check_tiling(const ltm_camera& c, const ltm_tiling& t)
+ltm_status check_tiling(const ltm_grid& g, const ltm_camera& c, const ltm_tiling& t)
 {
+    // the kernels form brick indices as FP32 sums of a grid coordinate times a
+    // brick stride (at most brick_floats); every such product must stay an
+    // exact FP32 integer
+    const uint64_t nmax = std::max<uint64_t>(g.nx, std::max<uint64_t>(g.ny, g.nz)) + 2;
+    if (nmax * std::max<uint64_t>(t.brick_floats, 1) >= (1ull << 24))
+        return fail(LTM_ERR_INVALID, "grid axis times brick_floats must stay below 2^24");
     if (t.tile_u == 0 || t.tile_v == 0 || t.splits == 0)
         return fail(LTM_ERR_INVALID, "tiling sizes must be positive");
     if (c.kind != LTM_PLENOPTIC && (t.block_u == 0 || t.block_v == 0))
@@ -231,7 +238,7 @@ ltm_tiling default_tiling(const ltm_grid& g, const ltm_camera& c, int dir)
     const uint64_t ku = c.kind == LTM_PLENOPTIC ? c.det_nu / c.mla_nu : t.block_u;
     const uint64_t kv = c.kind == LTM_PLENOPTIC ? c.det_nv / c.mla_nv : t.block_v;
     const uint64_t items = (uint64_t)t.tile_u * t.tile_v * ku * kv;
-    for (int guard = 0; guard < 64 && check_tiling(c, t) != LTM_OK; ++guard) {
+    for (int guard = 0; guard < 64 && check_tiling(g, c, t) != LTM_OK; ++guard) {
         const uint64_t per = (items + t.splits - 1) / t.splits;
         if (per > 8ull * kThreads || per * R > (uint64_t)kMaxRayList) {
             t.splits *= 2;
@@ -488,6 +495,8 @@ ltm_status ltm_plan_bind_workspace(ltm_plan* p, void* ws, uint64_t bytes, void* 
     if (reinterpret_cast<uintptr_t>(ws) % 256)
         return fail(LTM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
     p->ws = static_cast<char*>(ws);
+    p->bound = false;
+    ++p->generation;
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<TileRec> tiles;
     std::vector<BrickRec> bricks;
@@ -537,7 +546,7 @@ ltm_status ltm_plan_set_tiling(ltm_plan* p, uint32_t dir, uint32_t cam, const lt
 {
     if (!p || !t) return fail(LTM_ERR_INVALID, "null argument");
     if (dir > 1 || cam >= p->cams.size()) return fail(LTM_ERR_INVALID, "bad direction or camera");
-    ltm_status s = check_tiling(p->cams[cam].desc, *t);
+    ltm_status s = check_tiling(p->grid, p->cams[cam].desc, *t);
     if (s != LTM_OK) return s;
     p->cams[cam].tiling[dir] = *t;
     p->cams[cam].adapt[dir] = false;
@@ -545,6 +554,7 @@ ltm_status ltm_plan_set_tiling(ltm_plan* p, uint32_t dir, uint32_t cam, const lt
     layout(p);
     p->bound = false;
     p->ws = nullptr;
+    ++p->generation;
     clear_error();
     return LTM_OK;
 }

@@ -1,5 +1,6 @@
 // Host side of the reconstruction algorithm (the paper's reconstruction-
 // algorithm table) and of the regularizer entry point.
+#include <algorithm>
 #include <cmath>
 #include <new>
 #include <string>
@@ -85,7 +86,6 @@ ltm_status ltm_solver_create(ltm_plan* plan, const ltm_solver_params* prm, const
     if (!out) return fail(LTM_ERR_INVALID, "null output pointer");
     *out = nullptr;
     if (!plan || !prm || !y) return fail(LTM_ERR_INVALID, "null argument");
-    if (!plan->bound) return fail(LTM_ERR_WORKSPACE, "plan has no bound workspace");
     if (prm->psi_kind > LTM_PSI_HYPERBOLA) return fail(LTM_ERR_INVALID, "unknown potential");
     if (prm->n_subsets > 64) return fail(LTM_ERR_INVALID, "at most 64 view subsets");
     if (!(prm->beta >= 0.0) || !(prm->nu >= 0.0) || !(prm->c_r >= 0.0) || !std::isfinite(prm->beta) ||
@@ -93,6 +93,9 @@ ltm_status ltm_solver_create(ltm_plan* plan, const ltm_solver_params* prm, const
         return fail(LTM_ERR_INVALID, "beta, nu and c_R must be finite and nonnegative");
     if (prm->psi_kind == LTM_PSI_HYPERBOLA && !(prm->delta > 0.0 && std::isfinite(prm->delta)))
         return fail(LTM_ERR_INVALID, "the hyperbola potential needs delta > 0");
+    if (!(prm->rho_target >= 0.0) || !std::isfinite(prm->rho_target))
+        return fail(LTM_ERR_INVALID, "rho_target must be finite and nonnegative");
+    if (!plan->bound) return fail(LTM_ERR_WORKSPACE, "plan has no bound workspace");
     const Layout L = solver_layout(plan);
     if (!ws || ws_bytes < L.total)
         return fail(LTM_ERR_WORKSPACE, "solver workspace of " + std::to_string(L.total) +
@@ -187,6 +190,101 @@ ltm_status ltm_solver_reset(ltm_solver* s, const float* x0, void* stream)
     if (h == hipSuccess) h = solver_launch_reset(s->d, st);
     if (h != hipSuccess) return hip_fail(h, "solver reset");
     s->iter = 0;
+    return LTM_OK;
+}
+
+ltm_status ltm_solver_reset_warm(ltm_solver* s, const float* x0, double* alpha_out, double* rho_out,
+                                 uint32_t* accepted, void* stream)
+{
+    if (!s || !x0) return fail(LTM_ERR_INVALID, "null argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    SolverDev& d = s->d;
+    const int nc = d.n_cam;
+    // non-finite values of x0, then p = A x0 and its per-camera sums
+    hipError_t h = launch_count_nonfinite(x0, d.N, d.sc + SC_BAD, st);
+    if (h != hipSuccess) return hip_fail(h, "warm start check");
+    ltm_plan_set_ray_subset(s->plan, 1, 0);
+    ltm_status e = ltm_project(s->plan, x0, d.p, st);
+    if (e != LTM_OK) return e;
+    h = solver_launch_reduce(d, d.p, st);
+    std::vector<double> sc(SC_CAM + SC_NCAMARR * nc);
+    if (h == hipSuccess) h = hipMemcpyAsync(sc.data(), d.sc, 8 * sc.size(), hipMemcpyDeviceToHost, st);
+    if (h == hipSuccess) h = hipStreamSynchronize(st);
+    if (h != hipSuccess) return hip_fail(h, "warm start check");
+    const double* pp = &sc[SC_CAM + SC_PP * nc];
+    const double* yp = &sc[SC_CAM + SC_YP * nc];
+    const double* yy = &sc[SC_CAM + SC_YY * nc];
+    // least-squares scale of the image: camera 1 alone when the other
+    // cameras' gains are estimated (a gain absorbs any scale), else all
+    double spp = 0.0, syp = 0.0;
+    for (int c = 0; c < (d.gains ? 1 : nc); ++c) {
+        spp += pp[c];
+        syp += yp[c];
+    }
+    const double alpha = spp > 0.0 ? syp / spp : 0.0;
+    // rho(alpha x0) from the sums: p -> alpha p, gains re-estimated for it
+    double num = 0.0, den = 0.0;
+    for (int c = 0; c < nc; ++c) {
+        double g = 1.0;
+        if (d.gains && c > 0) g = yy[c] > 0.0 ? alpha * yp[c] / yy[c] : 0.0;
+        num += alpha * alpha * pp[c] - 2.0 * g * alpha * yp[c] + g * g * yy[c];
+        den += g * g * yy[c];
+    }
+    double rho = den > 0.0 ? std::sqrt(std::max(num, 0.0) / den) : INFINITY;
+    const bool ok = sc[SC_BAD] == 0.0 && std::isfinite(alpha) && alpha > 0.0 && std::isfinite(rho) &&
+                    rho < 1.0;
+    if (ok) {
+        h = launch_scale_copy(d.x, x0, (float)alpha, d.N, st);
+        if (h == hipSuccess) h = launch_copy(d.z, d.x, d.N, st);
+    } else {
+        rho = 1.0;
+        h = launch_fill(d.x, d.N, 0.0f, st);
+        if (h == hipSuccess) h = launch_fill(d.z, d.N, 0.0f, st);
+    }
+    if (h == hipSuccess) h = solver_launch_reset(d, st);
+    if (h != hipSuccess) return hip_fail(h, "warm start reset");
+    s->iter = 0;
+    if (alpha_out) *alpha_out = alpha;
+    if (rho_out) *rho_out = rho;
+    if (accepted) *accepted = ok ? 1u : 0u;
+    clear_error();
+    return LTM_OK;
+}
+
+ltm_status ltm_solver_solve(ltm_solver* s, uint32_t* iterations, uint32_t* converged, double* rho,
+                            void* stream)
+{
+    if (!s) return fail(LTM_ERR_INVALID, "null solver");
+    const uint32_t cap = s->prm.max_iter, every = s->prm.check_every;
+    if (cap == 0 || every == 0) return fail(LTM_ERR_INVALID, "max_iter and check_every must be >= 1");
+    const double target = s->prm.rho_target;
+    uint32_t it = 0;
+    bool conv = false;
+    double r = INFINITY;
+    while (it < cap) {
+        const uint32_t n = std::min(every, cap - it);
+        ltm_status e = ltm_solver_step(s, n, stream);
+        if (e != LTM_OK) return e;
+        it += n;
+        double rz = INFINITY;
+        e = ltm_solver_residual(s, &rz, nullptr, stream);
+        if (e != LTM_OK) return e;
+        if (target > 0.0 && rz <= target) {
+            e = ltm_solver_residual_x(s, &r, stream);
+            if (e != LTM_OK) return e;
+            if (r <= target) {
+                conv = true;
+                break;
+            }
+        }
+    }
+    if (!conv) {
+        ltm_status e = ltm_solver_residual_x(s, &r, stream);
+        if (e != LTM_OK) return e;
+    }
+    if (iterations) *iterations = it;
+    if (converged) *converged = conv ? 1u : 0u;
+    if (rho) *rho = r;
     return LTM_OK;
 }
 

@@ -12,6 +12,7 @@ enum {
     SC_RHO = 2,     // relative data residual at the last iteration's z
     SC_ITER = 3,    // iterations done
     SC_RHOX = 4,    // relative data residual at x (ltm_solver_residual_x)
+    SC_BAD = 5,     // non-finite values of a candidate start (ltm_solver_reset_warm)
     SC_CAM = 8      // per-camera arrays follow, n_cam entries each:
 };
 enum { SC_PP = 0, SC_YP = 1, SC_YY = 2, SC_GAMMA = 3, SC_NCAMARR = 4 };
@@ -37,6 +38,8 @@ hipError_t solver_launch_dinv(const SolverDev& d, float add, hipStream_t s);
 hipError_t solver_launch_reset(const SolverDev& d, hipStream_t s);
 hipError_t launch_copy(float* dst, const float* src, uint64_t n, hipStream_t s);
 hipError_t launch_mul(float* a, const float* w, uint64_t n, hipStream_t s);
+hipError_t launch_scale_copy(float* dst, const float* src, float a, uint64_t n, hipStream_t s);
+hipError_t launch_count_nonfinite(const float* v, uint64_t n, double* count, hipStream_t s);
 
 }  // namespace ltm
 

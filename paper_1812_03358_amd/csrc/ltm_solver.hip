@@ -205,6 +205,37 @@ __global__ void k_mul(float* __restrict__ a, const float* __restrict__ w, uint64
         a[i] *= w[i];
 }
 
+// dst = a * src.
+__global__ void k_scale_copy(float* __restrict__ dst, const float* __restrict__ src, float a, uint64_t n)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] = a * src[i];
+}
+
+// Number of non-finite values of v, added into *count (FP64 slot; one atomic
+// per block).
+__global__ __launch_bounds__(kRedThreads) void k_nonfinite(const float* __restrict__ v, uint64_t n,
+                                                           double* __restrict__ count)
+{
+    __shared__ unsigned int red[kRedThreads / 64];
+    unsigned int c = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * kRedThreads)
+        c += isfinite(v[i]) ? 0u : 1u;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int t = 0;
+        for (int k = 0; k < kRedThreads / 64; ++k) t += red[k];
+        if (t) unsafeAtomicAdd(count, (double)t);
+    }
+}
+
+__global__ void k_slot_zero(double* slot) { if (threadIdx.x == 0 && blockIdx.x == 0) *slot = 0.0; }
+
 __global__ void k_scalars_reset(double* sc, int n_cam, int gains)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -339,6 +370,19 @@ hipError_t solver_launch_reset(const SolverDev& d, hipStream_t s)
 hipError_t launch_copy(float* dst, const float* src, uint64_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_copy, dim3(grid1(n)), dim3(256), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_copy(float* dst, const float* src, float a, uint64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scale_copy, dim3(grid1(n)), dim3(256), 0, s, dst, src, a, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_nonfinite(const float* v, uint64_t n, double* count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_slot_zero, dim3(1), dim3(64), 0, s, count);
+    hipLaunchKernelGGL(k_nonfinite, dim3(grid1(n)), dim3(kRedThreads), 0, s, v, n, count);
     return hipGetLastError();
 }
 

@@ -36,7 +36,7 @@ class Grid(ctypes.Structure):
                 ("reserved", ctypes.c_uint32), ("pitch_mm", ctypes.c_double)]
 
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 
 class Camera(ctypes.Structure):
@@ -68,7 +68,9 @@ class SolverParams(ctypes.Structure):
     _fields_ = [("momentum", ctypes.c_uint32), ("gains", ctypes.c_uint32),
                 ("psi_kind", ctypes.c_uint32), ("n_subsets", ctypes.c_uint32),
                 ("beta", ctypes.c_double), ("delta", ctypes.c_double),
-                ("nu", ctypes.c_double), ("c_r", ctypes.c_double)]
+                ("nu", ctypes.c_double), ("c_r", ctypes.c_double),
+                ("rho_target", ctypes.c_double), ("max_iter", ctypes.c_uint32),
+                ("check_every", ctypes.c_uint32)]
 
 
 class ConvDesc(ctypes.Structure):
@@ -102,6 +104,10 @@ _SIGS = {
     "ltm_solver_destroy": (None, [_VP]),
     "ltm_solver_reset": (ctypes.c_int, [_VP, _VP, _VP]),
     "ltm_solver_step": (ctypes.c_int, [_VP, _U32, _VP]),
+    "ltm_solver_reset_warm": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_D), ctypes.POINTER(_D),
+                                             ctypes.POINTER(_U32), _VP]),
+    "ltm_solver_solve": (ctypes.c_int, [_VP, ctypes.POINTER(_U32), ctypes.POINTER(_U32),
+                                        ctypes.POINTER(_D), _VP]),
     "ltm_solver_get_x": (ctypes.c_int, [_VP, _VP, _VP]),
     "ltm_solver_residual": (ctypes.c_int, [_VP, ctypes.POINTER(_D), ctypes.POINTER(_U32), _VP]),
     "ltm_solver_residual_x": (ctypes.c_int, [_VP, ctypes.POINTER(_D), _VP]),
@@ -310,7 +316,8 @@ class Solver:
 
     def __init__(self, plan: Plan, y: torch.Tensor, w: torch.Tensor | None = None, *,
                  beta=0.0, delta=1.0, nu=0.0, c_r=36.0, psi_kind=PSI_QUADRATIC,
-                 momentum=True, gains=False, subsets=1, stream=None):
+                 momentum=True, gains=False, subsets=1, rho_target=0.0, max_iter=100,
+                 check_every=10, stream=None):
         self.plan = plan
         self.y = y
         self.w = w
@@ -318,7 +325,8 @@ class Solver:
         _check(lib().ltm_solver_workspace_bytes(plan.handle, ctypes.byref(b)))
         self.workspace = torch.empty(b.value, dtype=torch.uint8, device=y.device)
         self.params = SolverParams(int(momentum), int(gains), int(psi_kind), int(subsets),
-                                   float(beta), float(delta), float(nu), float(c_r))
+                                   float(beta), float(delta), float(nu), float(c_r),
+                                   float(rho_target), int(max_iter), int(check_every))
         h = ctypes.c_void_p()
         _check(lib().ltm_solver_create(plan.handle, ctypes.byref(self.params),
                                        _ptr(y, numel=plan.n_meas),
@@ -337,8 +345,25 @@ class Solver:
         _check(lib().ltm_solver_reset(self._h, _ptr(x0, numel=self.plan.n_voxels)
                                       if x0 is not None else None, _stream(stream)))
 
+    def reset_warm(self, x0: torch.Tensor, stream=None):
+        """Restart from a candidate start judged by the plain solver (see
+        ltm_solver_reset_warm): returns (accepted, alpha, rho(alpha x0))."""
+        a, r, ok = ctypes.c_double(), ctypes.c_double(), ctypes.c_uint32()
+        _check(lib().ltm_solver_reset_warm(self._h, _ptr(x0, numel=self.plan.n_voxels),
+                                           ctypes.byref(a), ctypes.byref(r), ctypes.byref(ok),
+                                           _stream(stream)))
+        return bool(ok.value), a.value, r.value
+
     def step(self, n_iter: int = 1, stream=None):
         _check(lib().ltm_solver_step(self._h, int(n_iter), _stream(stream)))
+
+    def solve(self, stream=None):
+        """Iterate until the stop rule (rho_target, max_iter, check_every):
+        returns (iterations, converged, rho of x)."""
+        it, conv, rho = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_double()
+        _check(lib().ltm_solver_solve(self._h, ctypes.byref(it), ctypes.byref(conv),
+                                      ctypes.byref(rho), _stream(stream)))
+        return it.value, bool(conv.value), rho.value
 
     def x(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         if out is None:

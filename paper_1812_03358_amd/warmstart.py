@@ -93,33 +93,29 @@ def train(net, plan, n, seeds, lr=1e-3, time_limit=None, workers=8, log=None, wa
 
 
 def solve_to(plan, y, x0=None, rho_target=1e-3, max_iter=5000, check_every=10, prelude=None):
-    """FISTA (beta = nu = 0) from x0 (None: zero) until rho <= target.
+    """FISTA (beta = nu = 0) from x0 (None: zero) until rho(x) <= target.
 
-    Wall-clock from the call (plan bound, y on the device) to the confirmed
-    residual of the iterate x; `prelude` (a callable returning x0) is timed
-    inside.  Returns dict(iterations, seconds, rho, converged)."""
+    The stop rule and the judgement of a warm start run in the library
+    (ltm_solver_solve, ltm_solver_reset_warm): a candidate start is rescaled
+    by the least-squares factor of its image and replaced by zero when it is
+    non-finite or does not lower the data residual below rho(0) = 1, so the
+    plain zero-start solver stays the fallback.  Wall-clock from the call
+    (plan bound, y on the device) to the confirmed residual of the iterate x;
+    `prelude` (a callable returning x0) is timed inside.  Returns
+    dict(iterations, seconds, rho, converged, accepted, alpha, rho0)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     if prelude is not None:
         x0 = prelude()
-    s = _ltm.Solver(plan, y, momentum=True)
-    s.reset(x0)
-    it = 0
-    rho = float("inf")
-    converged = False
-    while it < max_iter:
-        s.step(check_every)
-        it += check_every
-        rho_z, _ = s.residual()
-        if rho_z <= rho_target:
-            rho = s.residual_x()
-            if rho <= rho_target:
-                converged = True
-                break
-    if not converged:
-        rho = s.residual_x()
+    s = _ltm.Solver(plan, y, momentum=True, rho_target=rho_target, max_iter=max_iter,
+                    check_every=check_every)
+    accepted, alpha, rho0 = None, None, 1.0
+    if x0 is not None:
+        accepted, alpha, rho0 = s.reset_warm(x0)
+    it, converged, rho = s.solve()
     torch.cuda.synchronize()
-    return {"iterations": it, "seconds": time.perf_counter() - t0, "rho": rho, "converged": converged}
+    return {"iterations": it, "seconds": time.perf_counter() - t0, "rho": rho, "converged": converged,
+            "accepted": accepted, "alpha": alpha, "rho0": rho0}
 
 
 def compare(net, plan, n, seeds, rho_target=1e-3, max_iter=5000, check_every=10, log=None):

@@ -35,7 +35,7 @@ def test_every_declared_function_is_exported(L):
 
 
 def test_abi_version(L):
-    assert L.lib().ltm_abi_version() == L.ABI_VERSION == 2
+    assert L.lib().ltm_abi_version() == L.ABI_VERSION == 3
 
 
 def _create(L, g, cams):
@@ -99,11 +99,39 @@ def test_solver_requires_bound_plan(L):
     g = W.grid(8, 1.0)
     gg, cc, h = L.make_grid(g), L.make_cameras([W.single_lens_camera(8, (1, 1), 4)]), ctypes.c_void_p()
     assert L.lib().ltm_plan_create(ctypes.byref(gg), cc, 1, ctypes.byref(h)) == 0
-    prm = L.SolverParams(1, 0, 0, 0, 0.0, 1.0, 0.0, 36.0)
+    prm = L.SolverParams(1, 0, 0, 0, 0.0, 1.0, 0.0, 36.0, 1e-3, 100, 10)
     out = ctypes.c_void_p()
     st = L.lib().ltm_solver_create(h, ctypes.byref(prm), ctypes.c_void_p(256), None,
                                    ctypes.c_void_p(256), 1 << 20, None, ctypes.byref(out))
     assert st == L.LTM_ERR_WORKSPACE
+    # parameters are validated before anything else
+    prm.rho_target = -1.0
+    st = L.lib().ltm_solver_create(h, ctypes.byref(prm), ctypes.c_void_p(256), None,
+                                   ctypes.c_void_p(256), 1 << 20, None, ctypes.byref(out))
+    assert st == L.LTM_ERR_INVALID and "rho_target" in L.lib().ltm_last_error().decode()
+    L.lib().ltm_plan_destroy(h)
+
+
+def test_solver_entry_points_reject_null(L):
+    u, d = ctypes.c_uint32(), ctypes.c_double()
+    assert L.lib().ltm_solver_solve(None, ctypes.byref(u), ctypes.byref(u), ctypes.byref(d),
+                                    None) == L.LTM_ERR_INVALID
+    assert L.lib().ltm_solver_reset_warm(None, ctypes.c_void_p(256), None, None, None,
+                                         None) == L.LTM_ERR_INVALID
+
+
+def test_brick_index_range_is_checked(L):
+    # brick indices are FP32 sums of a grid coordinate times a brick stride:
+    # a 1100-voxel axis with 16384-float bricks would round them
+    g = W.grid((1100, 8, 8), 1.0)
+    gg, cc, h = L.make_grid(g), L.make_cameras([W.single_lens_camera(64, (1, 1), 8)]), ctypes.c_void_p()
+    assert L.lib().ltm_plan_create(ctypes.byref(gg), cc, 1, ctypes.byref(h)) == 0
+    t = L.Tiling()
+    assert L.lib().ltm_plan_get_tiling(h, 1, 0, ctypes.byref(t)) == 0
+    assert (1100 + 2) * t.brick_floats < (1 << 24)      # the default respects it
+    t.brick_floats = 16384
+    assert L.lib().ltm_plan_set_tiling(h, 1, 0, ctypes.byref(t)) == L.LTM_ERR_INVALID
+    assert "2^24" in L.lib().ltm_last_error().decode()
     L.lib().ltm_plan_destroy(h)
 
 

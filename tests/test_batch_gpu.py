@@ -141,3 +141,39 @@ def test_autotuner_candidates_pass_parity(orc, ltm):
     res = autotune.autotune_plan(plan, x, y, reps=2)
     assert all(r["ms"] <= r["default_ms"] for r in res)
     assert rel_l2(plan.project(x).cpu().numpy(), ref_y) < 1e-5
+
+
+def test_batch_detects_changed_member_plans(ltm):
+    """A batch records its plans' tables, workspaces and view subsets; after
+    a member plan is retuned, rebound or switched to another subset, every
+    batch entry point (graph launch included) refuses with
+    LTM_ERR_WORKSPACE instead of reading stale tables."""
+    frames = _frames()[:2]
+    plans, xs, ys, xts = _setup(ltm, frames)
+    b = ltm.Batch(plans, xs, ys, xts)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b.sweep(s)
+        b.capture(s)
+        b.replay(s)
+        s.synchronize()
+    plans[1].set_ray_subset(2, 1)
+    with pytest.raises(ltm.LtmError) as e:
+        b.sweep()
+    assert e.value.status == ltm.LTM_ERR_WORKSPACE
+    plans[1].set_ray_subset(1, 0)
+    b.sweep()                                       # back to the recorded subset
+    t = plans[0].get_tiling(1, 0).as_dict()
+    t["chunk_mm"] *= 0.5
+    plans[0].set_tiling(1, 0, t)                    # retuned and rebound
+    for call in (b.project, b.backproject, b.sweep, lambda: b.replay(s)):
+        with pytest.raises(ltm.LtmError) as e:
+            call()
+        assert e.value.status == ltm.LTM_ERR_WORKSPACE
+    torch.cuda.synchronize()
+    # a new batch over the changed plan works and matches the plan itself
+    b2 = ltm.Batch(plans, xs, ys, xts)
+    b2.sweep()
+    torch.cuda.synchronize()
+    ref = plans[0].backproject(ys[0])
+    assert rel_l2(xts[0].cpu().numpy(), ref.cpu().numpy()) < 1e-6

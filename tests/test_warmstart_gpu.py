@@ -34,3 +34,46 @@ def test_warm_start_small():
     warm = sum(r["warm"]["iterations"] for r in rows)
     assert all(r["zero"]["converged"] and r["warm"]["converged"] for r in rows)
     assert warm < zero
+
+
+def test_warm_start_fallback_and_rescale():
+    """The plain solver judges a candidate start: a NaN-holding one, a
+    negative one and one the cameras cannot see are replaced by the zero start
+    (the zero start's iterations); one scaled by 1e6 is brought back by the
+    least-squares factor of its image and still beats the zero start."""
+    from paper_1812_03358_amd import ltm, warmstart as WS
+    n = 32
+    g = W.grid(n, 160.0 / n)
+    cams = [W.plenoptic_camera(256, 16, (2, 2), 64, phi) for phi in (0.0, 90.0)]
+    plan = ltm.Plan(g, cams)
+    xt = torch.from_numpy(W.flame(n, 900004).reshape(-1)).cuda()
+    y = plan.project(xt).clone()
+    every = 5
+    kw = dict(rho_target=1e-3, max_iter=3000, check_every=every)
+    zero = WS.solve_to(plan, y, None, **kw)
+    print("zero start", zero, flush=True)
+    assert zero["converged"] and zero["accepted"] is None and zero["rho"] <= 1e-3
+    # a fair estimate: the truth times noise of 10%
+    rng = np.random.default_rng(5)
+    noisy = xt * torch.from_numpy(rng.uniform(0.9, 1.1, xt.numel()).astype(np.float32)).cuda()
+    good = WS.solve_to(plan, y, noisy, **kw)
+    print("fair start", good, flush=True)
+    assert good["accepted"] and abs(good["alpha"] - 1.0) < 0.05 and good["rho0"] < 0.2
+    assert good["converged"] and good["iterations"] < zero["iterations"]
+    # the same estimate at the wrong exposure: rescaled, the same solve
+    big = WS.solve_to(plan, y, noisy * 1e6, **kw)
+    print("fair start x 1e6", big, flush=True)
+    assert big["accepted"] and abs(big["alpha"] * 1e6 - good["alpha"]) < 1e-3 * good["alpha"]
+    assert abs(big["rho0"] - good["rho0"]) < 1e-4
+    assert big["converged"] and abs(big["iterations"] - good["iterations"]) <= every
+    # rejected starts run the zero start's solve
+    bad = noisy.clone()
+    bad[123] = float("nan")
+    D = plan.backproject(plan.project(torch.ones_like(xt)))
+    unseen = (D == 0).float()
+    assert float(unseen.sum()) > 0
+    for name, x0 in (("nan", bad), ("negative", -noisy), ("unseen", unseen)):
+        r = WS.solve_to(plan, y, x0, **kw)
+        print(name, r, flush=True)
+        assert r["accepted"] is False and r["rho0"] == 1.0
+        assert r["converged"] and abs(r["iterations"] - zero["iterations"]) <= every
