@@ -1,11 +1,15 @@
 #!/usr/bin/env python3
 """Throughput of the camera operator pair A x + A^T y on one MI355X.
 
-One step = one forward projection y = A x and one backprojection A^T y of
-the 128^3 flame volume seen by the 1024^2 plenoptic camera (64^2 lenslets,
-2x2 rays/pixel, 256 samples/ray), inputs resident in HBM.  The value is
-valid ray-samples per second over both operators (a sample is valid when its
-ray is unoccluded and crosses the grid).
+Default workload (batched_48): 48 flame frames (12 each of 96^3, 128^3,
+160^3 and 192^3 voxels) seen by 4 plenoptic cameras at 0/30/60/90 degrees
+(1024^2 pixels behind 64^2 lenslets, 2x2 rays per pixel, 2n samples per
+ray).  One step = one replay of a hipGraph holding the persistent forward
+sweep over all frames and cameras, then the persistent adjoint sweep; inputs
+resident in HBM.  The value is valid ray-samples per second over both
+directions (a sample is valid when its ray is unoccluded and crosses the
+grid).  Other workloads (--workload) time single plans, reconstructions,
+the learned warm start and the paper's own transport discretization.
 
 Prints one JSON line (see the repository's benchmark contract).
 """
@@ -27,9 +31,12 @@ sys.path.insert(0, ROOT)
 #   adjoint: position (6), fraction (3), 3 complements, 2 + 4 + 8
 #            weight products (17), 8 additions into the voxels (8)    -> 34
 FLOP_PER_SAMPLE = {"project": 31.0, "backproject": 34.0}
-# FP32 vector peak without packed-FP32 dual issue (the kernels are compiled without it):
-# 256 CUs x 4 SIMD x 16 lanes x 2 flop/FMA x 2.4 GHz
-PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# MI355X's published FP32 vector peak, 157.3 TFLOP/s = 256 CUs x 4 SIMD x 16
+# lanes x 2 flop/FMA x 2 (packed dual issue) x 2.4 GHz.  The kernels are
+# compiled without packed FP32, so 78.6 TFLOP/s is the ceiling they can reach;
+# the roofline fraction is still taken against the published figure.
+PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2 * 2 * 2.4e9 / 1e12
+PEAK_FP32_NON_PACKED_TFLOPS = PEAK_FP32_TFLOPS / 2
 HBM_PEAK_GBS = 8000.0
 GATHER_BYTES_PER_SAMPLE = 32.0   # 8 FP32 voxels per trilinear sample
 
@@ -136,6 +143,25 @@ def counter_traffic(plan, direction):
         return None
 
 
+def counter_traffic_batch(adjoint):
+    """HBM bytes per launch of k_batch on the 48-frame sweep from the
+    committed FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source
+    or the tuned table changed since the counters were taken."""
+    import hashlib
+
+    base = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(base, "profiles", "k_batch_batched_48_hbm_counters.md")
+    try:
+        line = [l for l in open(path) if l.startswith("provenance: ")][0]
+        prov = json.loads(line[len("provenance: "):])
+        for rel, h in prov["sha256_16"].items():
+            if hashlib.sha256(open(os.path.join(base, rel), "rb").read()).hexdigest()[:16] != h:
+                return None
+        return prov["traffic_bytes"]["backproject" if adjoint else "project"]
+    except (OSError, IndexError, KeyError, ValueError):
+        return None
+
+
 def roofline_of(valid, fwd_ms, adj_ms):
     dominant = "backproject" if adj_ms >= fwd_ms else "project"
     dom_ms = max(adj_ms, fwd_ms)
@@ -143,7 +169,8 @@ def roofline_of(valid, fwd_ms, adj_ms):
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_TFLOPS, 2),
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
             "kernel": "k_march<true> (adjoint)" if dominant == "backproject" else "k_march<false> (forward)",
-            "ms_per_launch": round(dom_ms, 4)}
+            "ms_per_launch": round(dom_ms, 4),
+            "frac_of_non_packed_fp32": round(achieved / PEAK_FP32_NON_PACKED_TFLOPS, 4)}
     gather = {d: round(valid / (ms * 1e-3) * GATHER_BYTES_PER_SAMPLE / 1e9 / HBM_PEAK_GBS, 4)
               for d, ms in (("project", fwd_ms), ("backproject", adj_ms))}
     return roof, gather
@@ -197,7 +224,8 @@ def run_single(args, cfg, workload, tune=False):
     tuned = None
     if tune and not args.no_autotune:
         t0 = time.perf_counter()
-        tuned = autotune.autotune_plan(plan, x, y, reps=2, cache=args.autotune_cache)
+        tuned = autotune.autotune_plan(plan, x, y, reps=2,
+                                       cache=args.autotune_cache or autotune.TUNED_TABLE)
         t_tune = time.perf_counter() - t0
         plan.project(x, y)
         torch.cuda.synchronize()
@@ -232,31 +260,104 @@ def run_single(args, cfg, workload, tune=False):
     return out
 
 
+def host_cpu():
+    """CPU model, logical CPUs of the host and the CPUs this process may use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, usable
+
+
+def oracle_threads():
+    """Threads the oracle may use: OMP_NUM_THREADS when set (a GPU job's
+    share of the host), else every CPU this process may use."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    _, _, usable = host_cpu()
+    return max(1, int(env)) if env.isdigit() and int(env) > 0 else usable
+
+
+def cpu_baseline_frames(units, threads, target_s):
+    """The FP64 oracle on a sample of a multi-frame, multi-camera workload.
+    units: (grid, cameras, volume, valid samples per direction of the frame);
+    for each frame the same fraction f of every camera's pixels is drawn,
+    projected (oracle.project_pixels per camera) and backprojected (one
+    oracle.backproject of the frame's image holding only those pixels, so its
+    per-thread volumes are reduced once per frame).  f doubles from a small
+    calibration pass until the sample takes about target_s.  Returns
+    (Gsamples/s over both directions, valid samples per direction in the
+    sample, forward s, adjoint s, f)."""
+    import numpy as np
+
+    import oracle
+
+    f = 1.0 / 512
+    while True:
+        t_fwd = t_adj = 0.0
+        valid = 0.0
+        for k, (g, cams, vol, frame_valid) in enumerate(units):
+            rng = np.random.default_rng(1000 + k)
+            x64 = np.asarray(vol, np.float64).reshape(-1)
+            img = []
+            for c in cams:
+                npix = c["det_nu"] * c["det_nv"]
+                pix = rng.choice(npix, size=max(1, int(round(f * npix))), replace=False)
+                t0 = time.perf_counter()
+                yv = oracle.project_pixels(g, c, x64, pix, threads)
+                t_fwd += time.perf_counter() - t0
+                im = np.zeros(npix)
+                im[pix] = yv + 1.0
+                img.append(im)
+            t0 = time.perf_counter()
+            oracle.backproject(g, cams, np.concatenate(img), threads)
+            t_adj += time.perf_counter() - t0
+            valid += f * frame_valid
+        if t_fwd + t_adj >= 0.45 * target_s or f >= 1.0:
+            break
+        f = min(1.0, f * max(2.0, min(16.0, 0.8 * target_s / max(t_fwd + t_adj, 1e-3))))
+    return 2.0 * valid / (t_fwd + t_adj) / 1e9, valid, t_fwd, t_adj, f
+
+
 def run_batched(args):
-    """48 frames x 4 plenoptic cameras: autotuned tilings, one graph replay
-    of the persistent A sweep then A^T sweep per step."""
+    """48 frames x 4 plenoptic cameras: tuned tilings, one graph replay of the
+    persistent A sweep then A^T sweep per step."""
     import numpy as np
     import torch
 
     from paper_1812_03358_amd import autotune, ltm, workloads as W
 
     frames = W.config_batched()
-    cache = args.autotune_cache or os.path.join("/tmp", "ltm_autotune_%d.json" % os.getpid())
-    plans, xs, ys, xts = [], [], [], []
+    cache = args.autotune_cache or autotune.TUNED_TABLE
+    plans, xs, ys, xts, vols = [], [], [], [], {}
     tuned = {}
     t0 = time.perf_counter()
     for f in frames:
         n = f["grid"]["nx"]
         p = ltm.Plan(f["grid"], f["cameras"])
-        x = torch.from_numpy(W.flame(n, f["volume_seed"]).reshape(-1)).cuda()
+        vol = W.flame(n, f["volume_seed"])
+        vols.setdefault(n, (f, vol))
+        x = torch.from_numpy(vol.reshape(-1)).cuda()
         y = torch.empty(p.n_meas, device="cuda")
-        if n not in tuned and not args.no_autotune:
-            p.project(x, y)
-            tuned[n] = autotune.autotune_plan(p, x, y, reps=2, cache=cache)
-        elif not args.no_autotune:
-            for ci in range(len(f["cameras"])):
-                for d in (0, 1):
-                    autotune.autotune(p, ci, d, x, y, cache=cache)
+        if not args.no_autotune:
+            if n not in tuned:
+                # one parity-gated tuning per volume size (the frames of a size
+                # share grid and cameras, hence their operator)
+                p.project(x, y)
+                tuned[n] = (p, autotune.autotune_plan(p, x, y, reps=2, cache=cache))
+            else:
+                src = tuned[n][0]
+                for ci in range(len(f["cameras"])):
+                    for d in (ltm.FORWARD, ltm.ADJOINT):
+                        p.set_tiling(d, ci, src.get_tiling(d, ci), rebind=False)
+                p.bind()
         plans.append(p)
         xs.append(x)
         ys.append(y)
@@ -274,21 +375,81 @@ def run_batched(args):
             batch.replay(s)
         s.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t_wall = time.perf_counter()
         a.record(s)
         for _ in range(args.steps):
             batch.replay(s)
         b.record(s)
         s.synchronize()
+        t_wall = time.perf_counter() - t_wall
+        # each direction's sweep alone, eagerly on the same stream: the
+        # persistent kernel's launch time (plus the adjoint's accumulator
+        # clear and FP32 conversion kernels, under 0.5% of it)
+        reps = max(2, min(args.steps, 5))
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+        for e in ev:
+            e[0].record(s)
+            batch.project(s)
+            e[1].record(s)
+            batch.backproject(s)
+            e[2].record(s)
+        s.synchronize()
     ms = a.elapsed_time(b) / args.steps
+    fwd_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / reps
+    adj_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / reps
     value = 2.0 * valid / (ms * 1e-3) / 1e9
     out = base_record(args, value, ms, "batched_48: 48 flame frames (12 each of 96/128/160/192^3, "
                       "160 mm cube) x 4 plenoptic cameras at 0/30/60/90 deg, 1024^2 px, 64^2 "
                       "lenslets, 2x2 rays, S = 2n; one hipGraph replay of the persistent A sweep "
-                      "and A^T sweep per step",
-                      {"valid_samples_per_direction": valid, "nominal_samples_per_direction": nominal})
-    out["setup_s_incl_autotune"] = round(t_setup, 2)
-    out["autotune"] = {str(n): [{"ms": round(r["ms"], 4), "default_ms": round(r["default_ms"], 4)}
-                                for r in res] for n, res in tuned.items()}
+                      "and A^T sweep per step" +
+                      ("" if args.no_autotune else "; tilings from the committed tuned table, "
+                       "each passed through the tuner's parity gate at set-up"),
+                      {"valid_samples_per_direction": valid, "nominal_samples_per_direction": nominal,
+                       "frames": len(frames), "cameras_per_frame": 4})
+    roof, gather = roofline_of(valid, fwd_ms, adj_ms)
+    roof["kernel"] = "k_batch<true> (adjoint sweep)" if adj_ms >= fwd_ms else "k_batch<false> (forward sweep)"
+    roof["traffic"] = counter_traffic_batch(adj_ms >= fwd_ms)
+    out["roofline"] = roof
+    out["gather_equivalent_hbm_frac_not_a_roofline"] = gather
+    out["ms_project_sweep"] = round(fwd_ms, 3)
+    out["ms_backproject_sweep"] = round(adj_ms, 3)
+    out["gsamples_per_s_project"] = round(valid / (fwd_ms * 1e-3) / 1e9, 2)
+    out["gsamples_per_s_backproject"] = round(valid / (adj_ms * 1e-3) / 1e9, 2)
+    out["wall_s_timed"] = round(t_wall, 3)
+    out["setup_s"] = round(t_setup, 2)
+    if tuned:
+        out["autotune"] = {str(n): [{"cam": r["camera"], "dir": r["direction"], "ms": round(r["ms"], 4),
+                                     "default_ms": round(r["default_ms"], 4)} for r in res]
+                           for n, (_, res) in tuned.items()}
+    if not args.no_cpu_baseline:
+        # one frame per volume size, all four cameras, extrapolated to the
+        # 48-frame sweep by valid-sample count
+        import oracle
+
+        model, logical, usable = host_cpu()
+        threads = oracle_threads()
+        units = []
+        for n in sorted(vols):
+            f, vol = vols[n]
+            frame_valid = sum(oracle.count_valid_rays(f["grid"], c, threads) * c["samples"]
+                              for c in f["cameras"])
+            units.append((f["grid"], f["cameras"], vol, frame_valid))
+        v_all, s_all, tf_all, ta_all, f_all = cpu_baseline_frames(units, threads, args.cpu_seconds)
+        v_one, s_one, tf_one, ta_one, f_one = cpu_baseline_frames(units, 1, args.cpu_seconds * 0.5)
+        out["cpu_baseline"] = {
+            "value": round(v_all, 4), "unit": "Gsamples/s", "cores": threads, "kind": "oracle",
+            "sample": (f"one frame of each size (96/128/160/192^3), all 4 cameras: a random "
+                       f"{f_all:.4f} of every camera's pixels, FP64 forward on them and FP64 "
+                       f"backprojection of the frame's image holding only them; {s_all:.3e} valid "
+                       f"samples per direction (that fraction of each frame's valid samples, "
+                       f"counted by the oracle); {tf_all:.1f} s + {ta_all:.1f} s on {threads} threads; "
+                       f"extrapolated by valid-sample count to the 48-frame sweep: "
+                       f"{2.0 * valid / (v_all * 1e9):.0f} s per A + A^T sweep"),
+            "one_core_value": round(v_one, 5),
+            "one_core_sample": (f"the same frames, fraction {f_one:.4f} of the pixels, 1 thread: "
+                                f"{tf_one:.1f} s + {ta_one:.1f} s; "
+                                f"{2.0 * valid / (v_one * 1e9) / 60:.0f} min per sweep extrapolated"),
+            "cpu_model": model, "host_logical_cpus": logical, "cpus_usable": usable}
     return out
 
 
@@ -683,13 +844,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="plenoptic_128",
+    ap.add_argument("--workload", default="batched_48",
                     choices=["plenoptic_128", "thin_lens_32", "differentiable_256", "batched_48",
                              "recon_plenoptic_128", "recon_three_camera_100", "warm_start_128",
                              "hex_plenoptic_100", "transport_100",
                              "plenoptic_transport_128", "warm_start_net_128"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=16.0)
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--autotune-cache", default=None)
     ap.add_argument("--no-autotune", action="store_true")

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LTM_ABI_VERSION 3u
+#define LTM_ABI_VERSION 4u
 
 typedef enum ltm_status {
     LTM_OK = 0,
@@ -131,7 +131,9 @@ typedef struct ltm_tiling {
     uint32_t order;
     uint32_t splits;
     uint32_t brick_floats;      /* 0: no LDS staging */
-    uint32_t reserved;
+    uint32_t groups_per_cu;     /* 0: as many workgroups per CU as registers and LDS allow;
+                                   k in 2..8: at most k (each group reserves more LDS than it
+                                   uses, 160 KiB / (k + 1) + 512 bytes) -- fewer waves per CU */
     double chunk_mm;
 } ltm_tiling;
 
@@ -196,6 +198,36 @@ ltm_status ltm_project(ltm_plan* plan, const float* x, float* y, void* stream);
  * rounded to FP32 and summed into an FP64 accumulator in the plan's
  * workspace, which is rounded to FP32 once at the end. */
 ltm_status ltm_backproject(ltm_plan* plan, const float* y, float* x, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Tilings chosen by measurement (an addition to the paper's method, whose
+ * own kernels had fixed shapes).  A tiling changes only how rays are grouped,
+ * staged and summed, so any tiling whose output matches the current one may
+ * be used.  For every camera and direction, ltm_autotune runs each candidate
+ * on a one-camera copy of the plan (the full operator, whatever view subset
+ * the plan is set to), on x (forward) or on the camera's block of y
+ * (adjoint); a candidate whose output differs from the current tiling's by
+ * more than 1e-6 relative L2 is rejected before it is timed.  The survivors
+ * are timed with HIP events on `stream` (median of `reps` runs after one
+ * untimed run).  Stage 1 searches tile size, lane order flags, slab depth
+ * and brick size (ltm_autotune_candidates lists them); stage 2 tries
+ * groups_per_cu = 2 and 3 on the three fastest.  The fastest passing tiling
+ * (the current one if nothing beats it) is set on the plan.
+ * cache_path (may be NULL): a text file of tilings keyed by GPU
+ * architecture, grid and camera descriptor.  A camera found there runs only
+ * its cached tiling, through the same parity gate, against the current one;
+ * searched results are added to the file (written to path.tmp, then renamed).
+ * ms (host, may be NULL): 4 doubles per camera -- forward best and current
+ * ms, adjoint best and current ms.
+ * Workspace: ltm_autotune_workspace_bytes (device, 256-byte aligned; the
+ * plan's own workspace is not touched).  The plan must be bound; it is left
+ * UNBOUND when any tiling changed -- query its workspace size and bind again.
+ * Synchronizes the stream many times. */
+ltm_status ltm_autotune_candidates(const ltm_plan* plan, uint32_t direction, uint32_t camera,
+                                   ltm_tiling* out, uint32_t capacity, uint32_t* count);
+ltm_status ltm_autotune_workspace_bytes(const ltm_plan* plan, uint64_t* bytes);
+ltm_status ltm_autotune(ltm_plan* plan, const float* x, const float* y, void* ws, uint64_t bytes,
+                        const char* cache_path, uint32_t reps, double* ms, void* stream);
 
 /* ---------------------------------------------------------------------- */
 /* Reconstruction: the paper's reconstruction-algorithm table (FISTA with a

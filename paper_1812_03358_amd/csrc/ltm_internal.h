@@ -15,6 +15,7 @@ constexpr int kThreads = 256;      // workgroup size of every ray kernel
 constexpr int kMaxRays = 64;       // R limit per pixel
 constexpr int kMaxBrickFloats = 16384;  // brick words (4 bytes)
 constexpr int kMaxLdsBytes = 65536;     // dynamic LDS of one march workgroup
+constexpr int kLdsPerCu = 163840;       // LDS of one gfx950 compute unit
 constexpr int kMaxRayList = 8192;       // valid rays one workgroup may own
 
 // Per-tile record: camera depth (relative to the anchor plane) where the
@@ -75,6 +76,7 @@ struct CamDev {
     int skew;             // adjoint: lanes start their sample walk at staggered offsets
     int merge;            // adjoint: merge consecutive samples of one cell in registers
     int window;           // adjoint: two planes of corner sums along the ray's dominant axis
+    int groups_per_cu;    // 0, or the most workgroups one CU may hold (LDS reservation)
     int sub_n, sub_i;     // angular-sample subset: keep r with r mod sub_n == sub_i
     int items, items_per_split, tiles_u, tiles_v, n_tiles;
     int brick_cap;        // LDS brick capacity in voxels (FP32 forward, FP64 adjoint)
@@ -144,12 +146,17 @@ hipError_t launch_project(const CamDev& c, const float* x, float* y, hipStream_t
 hipError_t launch_backproject(const CamDev& c, const float* y, double* x, hipStream_t s);
 hipError_t launch_fill64(double* p, uint64_t n, hipStream_t s);
 hipError_t launch_to_f32(const double* a, float* b, uint64_t n, hipStream_t s);
+// out[0] = sum (a - b)^2, out[1] = sum b^2 in FP64 (out: 2 doubles, cleared first)
+hipError_t launch_diff_sumsq(const float* a, const float* b, uint64_t n, double* out, hipStream_t s);
 hipError_t launch_fill(float* p, uint64_t n, float v, hipStream_t s);
 hipError_t launch_count(const CamDev& c, unsigned long long* counter, hipStream_t s);
 size_t march_lds_bytes(const CamDev& c, int dir);
 hipError_t launch_batch(const BatchCam* cams, const uint32_t* items, uint32_t n_items,
                         unsigned int* counter, int dir, int blocks, size_t lds, hipStream_t s);
 int batch_blocks_per_cu(int dir, size_t lds);
+
+// tiling limits (ltm_plan.cpp); sets the error message on failure
+ltm_status check_tiling(const ltm_grid& g, const ltm_camera& c, const ltm_tiling& t);
 
 // the camera's constants with the tables of one direction bound
 CamDev bound_dev(const ltm_plan* p, const CamHost& c, int dir);

@@ -139,40 +139,6 @@ uint64_t rays_per_pixel(const ltm_camera& c)
     return c.kind == LTM_PLENOPTIC_HEX ? 9 * R : R;
 }
 
-ltm_status check_tiling(const ltm_grid& g, const ltm_camera& c, const ltm_tiling& t)
-{
-    // the kernels form brick indices as FP32 sums of a grid coordinate times a
-    // brick stride (at most brick_floats); every such product must stay an
-    // exact FP32 integer
-    const uint64_t nmax = std::max<uint64_t>(g.nx, std::max<uint64_t>(g.ny, g.nz)) + 2;
-    if (nmax * std::max<uint64_t>(t.brick_floats, 1) >= (1ull << 24))
-        return fail(LTM_ERR_INVALID, "grid axis times brick_floats must stay below 2^24");
-    if (t.tile_u == 0 || t.tile_v == 0 || t.splits == 0)
-        return fail(LTM_ERR_INVALID, "tiling sizes must be positive");
-    if (c.kind != LTM_PLENOPTIC && (t.block_u == 0 || t.block_v == 0))
-        return fail(LTM_ERR_INVALID, "single-lens and hexagonal tilings need block sizes");
-    if (t.order > 63) return fail(LTM_ERR_INVALID, "tiling order flags must be 0..63");
-    if (t.brick_floats > (uint32_t)kMaxBrickFloats)
-        return fail(LTM_ERR_INVALID, "brick larger than 64 KiB of LDS");
-    if (!(t.chunk_mm > 0) || !std::isfinite(t.chunk_mm))
-        return fail(LTM_ERR_INVALID, "chunk_mm must be positive");
-    const uint64_t ku = c.kind == LTM_PLENOPTIC ? c.det_nu / c.mla_nu : t.block_u;
-    const uint64_t kv = c.kind == LTM_PLENOPTIC ? c.det_nv / c.mla_nv : t.block_v;
-    const uint64_t items = (uint64_t)t.tile_u * t.tile_v * ku * kv;
-    const uint64_t per = (items + t.splits - 1) / t.splits;
-    if (per == 0 || per > 8ull * kThreads)
-        return fail(LTM_ERR_INVALID, "a workgroup may own at most 2048 pixels of a tile");
-    const uint64_t R = rays_per_pixel(c);
-    if (per * R > (uint64_t)kMaxRayList)
-        return fail(LTM_ERR_INVALID, "a workgroup may own at most 8192 rays (pixels x R)");
-    const uint64_t lds = ((per * R * 4 + 15) & ~15ull) + ((per * 8 + 15) & ~15ull) +
-                         (uint64_t)t.brick_floats * 4;
-    if (lds > (uint64_t)kMaxLdsBytes)
-        return fail(LTM_ERR_INVALID, "ray list, pixel sums and brick exceed 64 KiB of LDS");
-    if (items > (1ull << 30)) return fail(LTM_ERR_INVALID, "tile too large");
-    return LTM_OK;
-}
-
 // The optical axis lies along none of the grid's axes.
 bool oblique(const ltm_camera& c)
 {
@@ -343,6 +309,7 @@ void apply_tiling(const ltm_grid& g, const ltm_camera& c, const ltm_tiling& t, C
     d.skew = (t.order & 8) ? 1 : 0;
     d.merge = (t.order & 16) ? 1 : 0;
     d.window = (t.order & 32) ? 1 : 0;
+    d.groups_per_cu = (int)t.groups_per_cu;
     d.splits = (int)t.splits;
     d.items = d.tile_u * d.tile_v * d.ku * d.kv;
     d.items_per_split = (d.items + d.splits - 1) / d.splits;
@@ -380,6 +347,42 @@ void layout(ltm_plan* p)
 }
 
 }  // namespace
+
+ltm_status check_tiling(const ltm_grid& g, const ltm_camera& c, const ltm_tiling& t)
+{
+    // the kernels form brick indices as FP32 sums of a grid coordinate times a
+    // brick stride (at most brick_floats); every such product must stay an
+    // exact FP32 integer
+    const uint64_t nmax = std::max<uint64_t>(g.nx, std::max<uint64_t>(g.ny, g.nz)) + 2;
+    if (nmax * std::max<uint64_t>(t.brick_floats, 1) >= (1ull << 24))
+        return fail(LTM_ERR_INVALID, "grid axis times brick_floats must stay below 2^24");
+    if (t.tile_u == 0 || t.tile_v == 0 || t.splits == 0)
+        return fail(LTM_ERR_INVALID, "tiling sizes must be positive");
+    if (c.kind != LTM_PLENOPTIC && (t.block_u == 0 || t.block_v == 0))
+        return fail(LTM_ERR_INVALID, "single-lens and hexagonal tilings need block sizes");
+    if (t.order > 63) return fail(LTM_ERR_INVALID, "tiling order flags must be 0..63");
+    if (t.groups_per_cu == 1 || t.groups_per_cu > 8)
+        return fail(LTM_ERR_INVALID, "groups_per_cu must be 0 or 2..8");
+    if (t.brick_floats > (uint32_t)kMaxBrickFloats)
+        return fail(LTM_ERR_INVALID, "brick larger than 64 KiB of LDS");
+    if (!(t.chunk_mm > 0) || !std::isfinite(t.chunk_mm))
+        return fail(LTM_ERR_INVALID, "chunk_mm must be positive");
+    const uint64_t ku = c.kind == LTM_PLENOPTIC ? c.det_nu / c.mla_nu : t.block_u;
+    const uint64_t kv = c.kind == LTM_PLENOPTIC ? c.det_nv / c.mla_nv : t.block_v;
+    const uint64_t items = (uint64_t)t.tile_u * t.tile_v * ku * kv;
+    const uint64_t per = (items + t.splits - 1) / t.splits;
+    if (per == 0 || per > 8ull * kThreads)
+        return fail(LTM_ERR_INVALID, "a workgroup may own at most 2048 pixels of a tile");
+    const uint64_t R = rays_per_pixel(c);
+    if (per * R > (uint64_t)kMaxRayList)
+        return fail(LTM_ERR_INVALID, "a workgroup may own at most 8192 rays (pixels x R)");
+    const uint64_t lds = ((per * R * 4 + 15) & ~15ull) + ((per * 8 + 15) & ~15ull) +
+                         (uint64_t)t.brick_floats * 4;
+    if (lds > (uint64_t)kMaxLdsBytes)
+        return fail(LTM_ERR_INVALID, "ray list, pixel sums and brick exceed 64 KiB of LDS");
+    if (items > (1ull << 30)) return fail(LTM_ERR_INVALID, "tile too large");
+    return LTM_OK;
+}
 
 ltm_status validate_cameras(const ltm_grid* g, const ltm_camera* cams, uint32_t n_cam)
 {

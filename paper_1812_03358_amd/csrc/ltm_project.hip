@@ -17,6 +17,7 @@
 // every (tile, slab) is computed once per plan by k_setup.
 #include "ltm_internal.h"
 
+#include <algorithm>
 #include <cfloat>
 
 namespace ltm {
@@ -862,6 +863,41 @@ __global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, ui
         b[i] = (float)a[i];
 }
 
+// out[0] += sum (a - b)^2, out[1] += sum b^2 (FP64; the autotuner's parity gate)
+__global__ void k_diff_sumsq(const float* __restrict__ a, const float* __restrict__ b, uint64_t n,
+                             double* __restrict__ out)
+{
+    double d2 = 0.0, b2 = 0.0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const double bv = b[i];
+        const double dv = (double)a[i] - bv;
+        d2 += dv * dv;
+        b2 += bv * bv;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        d2 += __shfl_down(d2, off, 64);
+        b2 += __shfl_down(b2, off, 64);
+    }
+    __shared__ double part[2][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        part[0][wave] = d2;
+        part[1][wave] = b2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int waves = (blockDim.x + 63) >> 6;
+        double s0 = 0.0, s1 = 0.0;
+        for (int w = 0; w < waves; ++w) {
+            s0 += part[0][w];
+            s1 += part[1][w];
+        }
+        atomicAdd(out, s0);
+        atomicAdd(out + 1, s1);
+    }
+}
+
 unsigned grid_for(uint64_t n)
 {
     uint64_t blocks = (n + 255) / 256;
@@ -902,7 +938,13 @@ size_t march_lds_bytes(const CamDev& c, int dir)
     const size_t list_bytes = ((size_t)c.items_per_split * c.ru * c.rv * 4 + 15) & ~size_t(15);
     const size_t item_bytes = ((size_t)c.items_per_split * 8 + 15) & ~size_t(15);
     const size_t brick_bytes = (size_t)c.brick_cap * ((dir == LTM_ADJOINT && !c.adj_f32) ? 8 : 4);
-    return list_bytes + item_bytes + brick_bytes;
+    size_t lds = list_bytes + item_bytes + brick_bytes;
+    if (c.groups_per_cu >= 2) {
+        // reserve enough that k + 1 groups cannot share one CU's LDS
+        const size_t cap = (size_t)kLdsPerCu / (size_t)(c.groups_per_cu + 1) + 512;
+        lds = std::max(lds, (cap + 15) & ~size_t(15));
+    }
+    return lds;
 }
 
 hipError_t launch_project(const CamDev& c, const float* x, float* y, hipStream_t s)
@@ -937,6 +979,15 @@ int batch_blocks_per_cu(int dir, size_t lds)
 hipError_t launch_fill64(double* p, uint64_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fill64, dim3(grid_for(n)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_diff_sumsq(const float* a, const float* b, uint64_t n, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill64, dim3(1), dim3(64), 0, s, out, (uint64_t)2);
+    unsigned blocks = grid_for(n);
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_diff_sumsq, dim3(blocks), dim3(256), 0, s, a, b, n, out);
     return hipGetLastError();
 }
 

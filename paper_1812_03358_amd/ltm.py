@@ -36,7 +36,7 @@ class Grid(ctypes.Structure):
                 ("reserved", ctypes.c_uint32), ("pitch_mm", ctypes.c_double)]
 
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 
 class Camera(ctypes.Structure):
@@ -57,11 +57,11 @@ class Tiling(ctypes.Structure):
     _fields_ = [("tile_u", ctypes.c_uint32), ("tile_v", ctypes.c_uint32),
                 ("block_u", ctypes.c_uint32), ("block_v", ctypes.c_uint32),
                 ("order", ctypes.c_uint32), ("splits", ctypes.c_uint32),
-                ("brick_floats", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("brick_floats", ctypes.c_uint32), ("groups_per_cu", ctypes.c_uint32),
                 ("chunk_mm", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class SolverParams(ctypes.Structure):
@@ -98,6 +98,10 @@ _SIGS = {
     "ltm_plan_set_ray_subset": (ctypes.c_int, [_VP, _U32, _U32]),
     "ltm_project": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "ltm_backproject": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "ltm_autotune_candidates": (ctypes.c_int, [_VP, _U32, _U32, _VP, _U32, ctypes.POINTER(_U32)]),
+    "ltm_autotune_workspace_bytes": (ctypes.c_int, [_VP, ctypes.POINTER(_U64)]),
+    "ltm_autotune": (ctypes.c_int, [_VP, _VP, _VP, _VP, _U64, ctypes.c_char_p, _U32,
+                                    ctypes.POINTER(_D), _VP]),
     "ltm_solver_workspace_bytes": (ctypes.c_int, [_VP, ctypes.POINTER(_U64)]),
     "ltm_solver_create": (ctypes.c_int, [_VP, ctypes.POINTER(SolverParams), _VP, _VP, _VP, _U64,
                                          _VP, ctypes.POINTER(_VP)]),

@@ -92,6 +92,19 @@ def train(net, plan, n, seeds, lr=1e-3, time_limit=None, workers=8, log=None, wa
     return {"steps": count, "seconds": time.perf_counter() - t0, "losses": losses}
 
 
+def held_out_loss(net, plan, n, seeds):
+    """Mean loss of the network's linear output over fixed volumes (no
+    weight update): the same volumes before and after training compare the
+    network itself, where single training steps see a different volume each."""
+    total = 0.0
+    for seed in seeds:
+        x = torch.from_numpy(W.flame(n, seed).reshape(-1)).to(net.device)
+        infer(net, plan, plan.project(x), n, final_relu=False)
+        loss, _ = net.loss_and_grad(x)
+        total += float(loss)
+    return total / len(seeds)
+
+
 def solve_to(plan, y, x0=None, rho_target=1e-3, max_iter=5000, check_every=10, prelude=None):
     """FISTA (beta = nu = 0) from x0 (None: zero) until rho(x) <= target.
 

@@ -35,7 +35,7 @@ def test_every_declared_function_is_exported(L):
 
 
 def test_abi_version(L):
-    assert L.lib().ltm_abi_version() == L.ABI_VERSION == 3
+    assert L.lib().ltm_abi_version() == L.ABI_VERSION == 4
 
 
 def _create(L, g, cams):
@@ -133,6 +133,50 @@ def test_brick_index_range_is_checked(L):
     assert L.lib().ltm_plan_set_tiling(h, 1, 0, ctypes.byref(t)) == L.LTM_ERR_INVALID
     assert "2^24" in L.lib().ltm_last_error().decode()
     L.lib().ltm_plan_destroy(h)
+
+
+def test_autotune_candidates_and_occupancy_field(L):
+    from paper_1812_03358_amd import autotune
+    cams = [W.plenoptic_camera(1024, 64, (2, 2), 256), W.single_lens_camera(64, (8, 8), 64)]
+    plan = L.Plan(W.grid(128, 1.25), cams, bind=False)
+    for ci in range(2):
+        for d in (0, 1):
+            cands = autotune.candidates(plan, ci, d)
+            assert len(cands) >= 8
+            assert len({tuple(sorted(c.items())) for c in cands}) == len(cands)
+            for c in cands:
+                assert c["groups_per_cu"] == 0
+                plan.set_tiling(d, ci, c, rebind=False)     # each one passes the checks
+    # the occupancy cap: 0 or 2..8
+    for cap, ok in ((0, True), (1, False), (2, True), (8, True), (9, False)):
+        t = plan.get_tiling(1, 0)
+        t.groups_per_cu = cap
+        st = L.lib().ltm_plan_set_tiling(plan.handle, 1, 0, ctypes.byref(t))
+        assert (st == 0) == ok, cap
+    nb = ctypes.c_uint64()
+    assert L.lib().ltm_autotune_workspace_bytes(plan.handle, ctypes.byref(nb)) == 0
+    assert nb.value >= 2 * 4 * 128 ** 3 + 8 * 128 ** 3      # two volumes and an accumulator
+    ms = (ctypes.c_double * 8)()
+    assert L.lib().ltm_autotune(plan.handle, None, ctypes.c_void_p(256), ctypes.c_void_p(256),
+                                nb.value, None, 2, ms, None) == L.LTM_ERR_INVALID
+    assert L.lib().ltm_autotune(plan.handle, ctypes.c_void_p(256), ctypes.c_void_p(256),
+                                ctypes.c_void_p(256), nb.value, None, 0, ms, None) == L.LTM_ERR_INVALID
+    assert L.lib().ltm_autotune(plan.handle, ctypes.c_void_p(256), ctypes.c_void_p(256),
+                                ctypes.c_void_p(8), nb.value, None, 2, ms, None) == L.LTM_ERR_WORKSPACE
+
+
+def test_tuned_table_parses():
+    from paper_1812_03358_amd import autotune
+    if not os.path.exists(autotune.TUNED_TABLE):
+        pytest.skip("no tuned table committed")
+    rows = [l.rstrip("\n").split("\t") for l in open(autotune.TUNED_TABLE) if not l.startswith("#")]
+    assert rows
+    for key, tiling, times in rows:
+        assert key.startswith("gfx950|")
+        f = tiling.split()
+        assert len(f) == 9 and all(v.isdigit() for v in f[:8]) and float(f[8]) > 0
+        best, default = map(float, times.split())
+        assert 0 < best <= default
 
 
 def test_binding_fails_loudly_without_library(L, monkeypatch, tmp_path):

@@ -138,9 +138,16 @@ def test_autotuner_candidates_pass_parity(orc, ltm):
                 continue
             out = plan.project(x) if d == 0 else plan.backproject(y)
             assert rel_l2(out.cpu().numpy(), ref) < 1e-5, cand
+        # stage 2's occupancy caps reserve LDS only: same samples, same sums
+        for cap in (2, 3):
+            t = dict(autotune.candidates(plan, 0, d)[0], groups_per_cu=cap)
+            plan.set_tiling(d, 0, t)
+            out = plan.project(x) if d == 0 else plan.backproject(y)
+            assert rel_l2(out.cpu().numpy(), ref) < 1e-5, t
     res = autotune.autotune_plan(plan, x, y, reps=2)
     assert all(r["ms"] <= r["default_ms"] for r in res)
     assert rel_l2(plan.project(x).cpu().numpy(), ref_y) < 1e-5
+    assert rel_l2(plan.backproject(y).cpu().numpy(), ref_x) < 1e-5
 
 
 def test_batch_detects_changed_member_plans(ltm):

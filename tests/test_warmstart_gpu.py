@@ -23,11 +23,13 @@ def test_warm_start_small():
     cams = [W.plenoptic_camera(256, 16, (2, 2), 64, phi) for phi in (0.0, 90.0)]
     plan = ltm.Plan(g, cams)
     net = nn.UNet(seed=1)
+    held_out = [900101, 900102, 900103, 900104]
+    before = WS.held_out_loss(net, plan, n, held_out)
     tr = WS.train(net, plan, n, range(0, 400), lr=2e-3, workers=4)
-    first, last = tr["losses"][0][1], tr["losses"][-1][1]
-    print("train", tr["steps"], "steps, loss", first, "->", last, flush=True)
+    after = WS.held_out_loss(net, plan, n, held_out)
+    print("train", tr["steps"], "steps, held-out loss", before, "->", after, flush=True)
     assert tr["steps"] == 400
-    assert last < 0.5 * first
+    assert after < 0.5 * before
     rows = WS.compare(net, plan, n, [900001, 900002, 900003], rho_target=1e-3, max_iter=3000,
                       check_every=5, log=print)
     zero = sum(r["zero"]["iterations"] for r in rows)
