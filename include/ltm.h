@@ -199,6 +199,25 @@ ltm_status ltm_project(ltm_plan* plan, const float* x, float* y, void* stream);
  * workspace, which is rounded to FP32 once at the end. */
 ltm_status ltm_backproject(ltm_plan* plan, const float* y, float* x, void* stream);
 
+/* For callers that cannot allocate device memory at the call (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * ltm_backproject with the FP64 accumulator taken from a fixed array the
+ * library holds on each GPU (2^23 doubles = 64 MiB, reserved when the
+ * library's code is loaded on that GPU and kept until the process ends)
+ * instead of from the plan's workspace.  Same kernels, samples and weights,
+ * so the same result as ltm_backproject.  The plan must still be bound (its
+ * tile tables live in the workspace); y, x and the stream are as for
+ * ltm_backproject, on the current device.  Errors: LTM_ERR_INVALID when the
+ * plan has more than 2^23 = 8388608 voxels (checked before anything else
+ * than the null arguments, with no device call), LTM_ERR_WORKSPACE when the
+ * plan is unbound, LTM_ERR_DEVICE when the array's address cannot be read.
+ * Allocates nothing: the first call on a GPU only looks the array's address
+ * up.  Every call on one GPU shares that GPU's array; each call clears the
+ * part it uses on its stream first, so calls ordered on one stream are
+ * safe, while calls that overlap on one GPU (other streams, other threads)
+ * race and give wrong results. */
+ltm_status ltm_backproject_noalloc(ltm_plan* plan, const float* y, float* x, void* stream);
+
 /* ---------------------------------------------------------------------- */
 /* Tilings chosen by measurement (an addition to the paper's method, whose
  * own kernels had fixed shapes).  A tiling changes only how rays are grouped,

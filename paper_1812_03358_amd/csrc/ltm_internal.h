@@ -17,6 +17,8 @@ constexpr int kMaxBrickFloats = 16384;  // brick words (4 bytes)
 constexpr int kMaxLdsBytes = 65536;     // dynamic LDS of one march workgroup
 constexpr int kLdsPerCu = 163840;       // LDS of one gfx950 compute unit
 constexpr int kMaxRayList = 8192;       // valid rays one workgroup may own
+// voxels of the fixed FP64 accumulator behind ltm_backproject_noalloc
+constexpr uint64_t kScratchVoxels = uint64_t(1) << 23;
 
 // Per-tile record: camera depth (relative to the anchor plane) where the
 // tile's first slab starts, and its number of slabs.
@@ -145,6 +147,8 @@ hipError_t launch_setup(const CamDev& c, int dir, hipStream_t s);
 hipError_t launch_project(const CamDev& c, const float* x, float* y, hipStream_t s);
 hipError_t launch_backproject(const CamDev& c, const float* y, double* x, hipStream_t s);
 hipError_t launch_fill64(double* p, uint64_t n, hipStream_t s);
+// device address of the current GPU's fixed accumulator (kScratchVoxels doubles)
+hipError_t scratch_accumulator(double** out);
 hipError_t launch_to_f32(const double* a, float* b, uint64_t n, hipStream_t s);
 // out[0] = sum (a - b)^2, out[1] = sum b^2 in FP64 (out: 2 doubles, cleared first)
 hipError_t launch_diff_sumsq(const float* a, const float* b, uint64_t n, double* out, hipStream_t s);

@@ -618,4 +618,27 @@ ltm_status ltm_backproject(ltm_plan* p, const float* y, float* x, void* stream)
     return LTM_OK;
 }
 
+ltm_status ltm_backproject_noalloc(ltm_plan* p, const float* y, float* x, void* stream)
+{
+    if (!p || !x || !y) return fail(LTM_ERR_INVALID, "null argument");
+    if (p->n_vox > kScratchVoxels)
+        return fail(LTM_ERR_INVALID, "volume of " + std::to_string(p->n_vox) +
+                                         " voxels exceeds the fixed accumulator's " +
+                                         std::to_string(kScratchVoxels));
+    if (!p->bound) return fail(LTM_ERR_WORKSPACE, "plan has no bound workspace");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* acc = nullptr;
+    hipError_t e = scratch_accumulator(&acc);
+    if (e != hipSuccess) return hip_fail(e, "fixed accumulator address");
+    e = launch_fill64(acc, p->n_vox, s);
+    if (e != hipSuccess) return hip_fail(e, "zero accumulator");
+    for (auto& c : p->cams) {
+        e = launch_backproject(bound_dev(p, c, LTM_ADJOINT), y, acc, s);
+        if (e != hipSuccess) return hip_fail(e, "backproject");
+    }
+    e = launch_to_f32(acc, x, p->n_vox, s);
+    if (e != hipSuccess) return hip_fail(e, "convert");
+    return LTM_OK;
+}
+
 }  // extern "C"

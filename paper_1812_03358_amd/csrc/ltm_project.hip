@@ -19,8 +19,38 @@
 
 #include <algorithm>
 #include <cfloat>
+#include <mutex>
+
+// Fixed FP64 adjoint accumulator of ltm_backproject_noalloc (kScratchVoxels
+// doubles, 64 MiB per GPU, held until the process ends).  Host code never
+// passes this name to a kernel: it is a host-side stand-in there, and the
+// device address comes from hipGetSymbolAddress below.
+static __device__ __align__(256) double scratch[ltm::kScratchVoxels];
 
 namespace ltm {
+
+// Device address of this GPU's copy of `scratch`, looked up once per device
+// (with that device current) and kept.
+hipError_t scratch_accumulator(double** out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double* addr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = static_cast<double*>(p);
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
 
 namespace {
 

@@ -98,6 +98,7 @@ _SIGS = {
     "ltm_plan_set_ray_subset": (ctypes.c_int, [_VP, _U32, _U32]),
     "ltm_project": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "ltm_backproject": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "ltm_backproject_noalloc": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "ltm_autotune_candidates": (ctypes.c_int, [_VP, _U32, _U32, _VP, _U32, ctypes.POINTER(_U32)]),
     "ltm_autotune_workspace_bytes": (ctypes.c_int, [_VP, ctypes.POINTER(_U64)]),
     "ltm_autotune": (ctypes.c_int, [_VP, _VP, _VP, _VP, _U64, ctypes.c_char_p, _U32,
@@ -312,6 +313,13 @@ class Plan:
             x = torch.empty(self.n_voxels, dtype=torch.float32, device=y.device)
         _check(lib().ltm_backproject(self._h, _ptr(y, numel=self.n_meas),
                                      _ptr(x, numel=self.n_voxels), _stream(stream)))
+        return x
+
+    def backproject_noalloc(self, y: torch.Tensor, x: torch.Tensor, stream=None) -> torch.Tensor:
+        """A^T y through ltm_backproject_noalloc (the library's fixed
+        accumulator instead of the workspace's); x must be given."""
+        _check(lib().ltm_backproject_noalloc(self._h, _ptr(y, numel=self.n_meas),
+                                             _ptr(x, numel=self.n_voxels), _stream(stream)))
         return x
 
 

@@ -135,6 +135,27 @@ def test_brick_index_range_is_checked(L):
     L.lib().ltm_plan_destroy(h)
 
 
+def test_noalloc_backproject_rejects_before_any_device_call(L):
+    # the fixed accumulator holds 2^23 doubles: 204^3 = 8489664 voxels is one
+    # plan too many, refused before the plan's binding is even looked at
+    cam = [W.single_lens_camera(64, (1, 1), 8)]
+    big = W.grid(204, 1.0)
+    gg, cc, h = L.make_grid(big), L.make_cameras(cam), ctypes.c_void_p()
+    assert L.lib().ltm_plan_create(ctypes.byref(gg), cc, 1, ctypes.byref(h)) == 0
+    st = L.lib().ltm_backproject_noalloc(h, ctypes.c_void_p(256), ctypes.c_void_p(256), None)
+    assert st == L.LTM_ERR_INVALID
+    assert "8388608" in L.lib().ltm_last_error().decode()
+    assert L.lib().ltm_backproject_noalloc(h, None, ctypes.c_void_p(256), None) == L.LTM_ERR_INVALID
+    L.lib().ltm_plan_destroy(h)
+    # 203^3 = 8365427 fits; the unbound plan is then refused
+    ok = W.grid(203, 1.0)
+    gg = L.make_grid(ok)
+    assert L.lib().ltm_plan_create(ctypes.byref(gg), cc, 1, ctypes.byref(h)) == 0
+    st = L.lib().ltm_backproject_noalloc(h, ctypes.c_void_p(256), ctypes.c_void_p(256), None)
+    assert st == L.LTM_ERR_WORKSPACE
+    L.lib().ltm_plan_destroy(h)
+
+
 def test_autotune_candidates_and_occupancy_field(L):
     from paper_1812_03358_amd import autotune
     cams = [W.plenoptic_camera(1024, 64, (2, 2), 256), W.single_lens_camera(64, (8, 8), 64)]
