@@ -417,6 +417,8 @@ def run_batched(args):
     out["gsamples_per_s_backproject"] = round(valid / (adj_ms * 1e-3) / 1e9, 2)
     out["wall_s_timed"] = round(t_wall, 3)
     out["setup_s"] = round(t_setup, 2)
+    if args.copy_probe:
+        copy_probe()
     if tuned:
         out["autotune"] = {str(n): [{"cam": r["camera"], "dir": r["direction"], "ms": round(r["ms"], 4),
                                      "default_ms": round(r["default_ms"], 4)} for r in res]
