@@ -120,7 +120,9 @@ typedef struct ltm_camera {
  * bit 4 (adjoint) merges consecutive samples of one trilinear cell in
  * registers before the LDS atomics; bit 5 (adjoint) instead keeps two planes
  * of corner sums across the ray's dominant axis, so a step along that axis
- * flushes 4 corners, not 8.  Each workgroup
+ * flushes 4 corners, not 8; bit 6 (with bit 3) makes the staggered starting
+ * offsets even, so rays that advance half a voxel per sample along that axis
+ * cross its cell planes on the same iterations.  Each workgroup
  * marches its rays through consecutive slabs of chunk_mm camera depth,
  * staging the voxels the slab's rays touch in an LDS brick of at most
  * brick_floats floats (a slab whose brick does not fit uses global memory).

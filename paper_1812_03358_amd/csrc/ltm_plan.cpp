@@ -306,7 +306,7 @@ void apply_tiling(const ltm_grid& g, const ltm_camera& c, const ltm_tiling& t, C
     d.order = (int)t.order;
     d.rotate = (t.order & 2) ? 0 : 1;
     d.adj_f32 = (t.order & 4) ? 1 : 0;
-    d.skew = (t.order & 8) ? 1 : 0;
+    d.skew = (t.order & 8) ? ((t.order & 64) ? 2 : 1) : 0;
     d.merge = (t.order & 16) ? 1 : 0;
     d.window = (t.order & 32) ? 1 : 0;
     d.groups_per_cu = (int)t.groups_per_cu;
@@ -360,7 +360,7 @@ ltm_status check_tiling(const ltm_grid& g, const ltm_camera& c, const ltm_tiling
         return fail(LTM_ERR_INVALID, "tiling sizes must be positive");
     if (c.kind != LTM_PLENOPTIC && (t.block_u == 0 || t.block_v == 0))
         return fail(LTM_ERR_INVALID, "single-lens and hexagonal tilings need block sizes");
-    if (t.order > 63) return fail(LTM_ERR_INVALID, "tiling order flags must be 0..63");
+    if (t.order > 127) return fail(LTM_ERR_INVALID, "tiling order flags must be 0..127");
     if (t.groups_per_cu == 1 || t.groups_per_cu > 8)
         return fail(LTM_ERR_INVALID, "groups_per_cu must be 0 or 2..8");
     if (t.brick_floats > (uint32_t)kMaxBrickFloats)

@@ -559,9 +559,16 @@ __device__ __forceinline__ void scatter_lds_merged(const March& mr, int m0, int 
 // cell's low (or high) plane; any other move flushes both planes.  Rays
 // advance about half a voxel per sample, mostly along c, so most cell
 // changes flush 4 corners instead of 8.
+//
+// A wave runs the flush code whenever any of its lanes changes cell, so the
+// cost follows how many iterations see a change in some lane.  With skew = 2
+// the lanes' staggered starting offsets are even: rays that cross the whole
+// grid along c advance exactly half a voxel per sample and cross c-planes at
+// samples of one parity, so even offsets keep their c-crossings on the same
+// iterations while the lanes still sit at different depths.
 template <typename T>
 __device__ __forceinline__ void scatter_lds_window(const March& mr, int m0, int m1, const BrickRec& b,
-                                                   T* brick, float v, bool skew)
+                                                   T* brick, float v, int skew)
 {
     const int sx = b.dim[0], sxy = b.dim[0] * b.dim[1];
     const float maxi = (float)(b.dim[0] * b.dim[1] * b.dim[2] - 1 - (1 + sx + sxy));
@@ -576,34 +583,43 @@ __device__ __forceinline__ void scatter_lds_window(const March& mr, int m0, int 
     const float qc0 = c == 0 ? mr.qs[0] : (c == 1 ? mr.qs[1] : mr.qs[2]);
     const float dc = c == 0 ? mr.st[0] : (c == 1 ? mr.st[1] : mr.st[2]);
     const float fsa = (float)sa, fsb = (float)sb, fsc = (float)sc, nbase = -b.base;
+    // byte strides of the corners from a cell's low corner
+    char* const bytes = reinterpret_cast<char*>(brick);
+    const int ba = sa * (int)sizeof(T), bb = sb * (int)sizeof(T), bab = ba + bb;
+    const int bc = sc * (int)sizeof(T);
     const int cnt = m1 - m0;
-    int m = m0;
-    if (skew) m += (int)(((threadIdx.x & 63) * (unsigned)cnt) >> 6);
-    // the sample index counts in FP32 (exact below 2^24) and wraps at m1
-    float fm = (float)m;
-    const float fm0 = (float)m0, fm1 = (float)m1;
-    int cur = -1;
-    float lo[4] = {0.f, 0.f, 0.f, 0.f}, hi[4] = {0.f, 0.f, 0.f, 0.f};
-    auto flush4 = [&](int i, const float (&p)[4]) {
-        T* q = brick + i;
-        atomicAdd(q, (T)p[0]);
-        atomicAdd(q + sa, (T)p[1]);
-        atomicAdd(q + sb, (T)p[2]);
-        atomicAdd(q + sa + sb, (T)p[3]);
-    };
-    for (int k = 0; k < cnt; ++k) {
+    int off = 0;
+    if (skew) {
+        off = (int)(((threadIdx.x & 63) * (unsigned)cnt) >> 6);
+        if (skew == 2) off &= ~1;
+    }
+    // the cell's LDS index: exact integer arithmetic in FP32 (brick indices < 2^24)
+    auto cell = [&](float fm, float& fa, float& fb, float& fc) {
         const float qa = fmaf(fm, da, qa0), qb = fmaf(fm, db, qb0), qc = fmaf(fm, dc, qc0);
         const float ca = floorf(qa), cb = floorf(qb), cc = floorf(qc);
-        const float fa = qa - ca, fb = qb - cb, fc = qc - cc;
-        // the cell's LDS index: exact integer arithmetic in FP32 (brick indices < 2^24)
+        fa = qa - ca;
+        fb = qb - cb;
+        fc = qc - cc;
         const float fi = fmaf(cc, fsc, fmaf(cb, fsb, fmaf(ca, fsa, nbase)));
-        const int i0 = (int)clampf(fi, 0.0f, maxi);
+        return (int)clampf(fi, 0.0f, maxi);
+    };
+    float lo[4] = {0.f, 0.f, 0.f, 0.f}, hi[4] = {0.f, 0.f, 0.f, 0.f};
+    auto flush4 = [&](int i, const float (&p)[4]) {
+        char* q = bytes + i * (int)sizeof(T);
+        atomicAdd(reinterpret_cast<T*>(q), (T)p[0]);
+        atomicAdd(reinterpret_cast<T*>(q + ba), (T)p[1]);
+        atomicAdd(reinterpret_cast<T*>(q + bb), (T)p[2]);
+        atomicAdd(reinterpret_cast<T*>(q + bab), (T)p[3]);
+    };
+    // the window starts at the first sample's cell
+    float fa, fb, fc;
+    int cur = cell((float)(m0 + off), fa, fb, fc);
+    auto step = [&](float fm) {
+        const int i0 = cell(fm, fa, fb, fc);
         if (i0 != cur) {
             const bool up = i0 == cur + sc, down = i0 == cur - sc;
-            if (cur >= 0) {
-                if (!down) flush4(cur, lo);
-                if (!up) flush4(cur + sc, hi);
-            }
+            if (!down) flush4(cur, lo);
+            if (!up) flush4(cur + sc, hi);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const float l = lo[j];
@@ -613,17 +629,25 @@ __device__ __forceinline__ void scatter_lds_window(const March& mr, int m0, int 
             cur = i0;
         }
         const float ga = 1.0f - fa, gb = 1.0f - fb;
-        const float vl = v * (1.0f - fc), vh = v * fc;
+        const float vh = v * fc, vl = v - vh;
         const float w[4] = {ga * gb, fa * gb, ga * fb, fa * fb};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             lo[j] = fmaf(vl, w[j], lo[j]);
             hi[j] = fmaf(vh, w[j], hi[j]);
         }
+    };
+    // the sample index counts in FP32 (exact below 2^24) from m0 + off and
+    // wraps at m1 back to m0: every lane runs cnt iterations, so a wave's
+    // lanes stay busy together
+    float fm = (float)(m0 + off);
+    const float fm0 = (float)m0, fm1 = (float)m1;
+    for (int k = 0; k < cnt; ++k) {
+        step(fm);
         fm += 1.0f;
         fm = fm == fm1 ? fm0 : fm;
     }
-    if (cur >= 0) {
+    if (cnt > 0) {
         flush4(cur, lo);
         flush4(cur + sc, hi);
     }

@@ -165,8 +165,8 @@ std::vector<ltm_tiling> shape_candidates(const ltm_grid& g, const ltm_camera& c,
                     const uint64_t splits = std::max<uint64_t>(1, items / per);
                     if (items % splits || items / splits > 2048 || items / splits * R > 8192) continue;
                     // bits: 0 lanes across lenslets, 1 no rotation, 3 staggered walks,
-                    // 4 merged cells, 5 plane windows
-                    for (uint32_t order : {3u, 26u, 27u, 42u, 43u})
+                    // 4 merged cells, 5 plane windows, 6 even stagger offsets
+                    for (uint32_t order : {26u, 27u, 40u, 41u, 42u, 43u, 104u, 105u, 106u, 107u})
                         for (double chunk : {16.0, 32.0})
                             for (uint32_t brick : {8192u, 12288u})
                                 push(t, blk, order, (uint32_t)splits, brick, chunk);

@@ -32,16 +32,18 @@ def workloads():
 
 def main(path: str) -> None:
     for name, g, cams, vol in workloads():
-        t0 = time.perf_counter()
-        plan = ltm.Plan(g, cams)
         x = torch.from_numpy(vol.reshape(-1)).cuda()
-        y = plan.project(x)
-        res = autotune.autotune_plan(plan, x, y, reps=3, cache=path)
-        torch.cuda.synchronize()
-        print(f"{name}: {time.perf_counter() - t0:.1f} s", flush=True)
-        for r in res:
-            print(f"  camera {r['camera']} {'A ' if r['direction'] == 0 else 'AT'} "
-                  f"{r['ms']:.4f} ms (default {r['default_ms']:.4f}) {r['tiling']}", flush=True)
+        # one camera at a time (the table is keyed per camera and grid)
+        for k, cam in enumerate(cams):
+            t0 = time.perf_counter()
+            plan = ltm.Plan(g, [cam])
+            y = plan.project(x)
+            res = autotune.autotune_plan(plan, x, y, reps=3, cache=path)
+            torch.cuda.synchronize()
+            print(f"{name} camera {k}: {time.perf_counter() - t0:.1f} s", flush=True)
+            for r in res:
+                print(f"  {'A ' if r['direction'] == 0 else 'AT'} {r['ms']:.4f} ms "
+                      f"(default {r['default_ms']:.4f}) {r['tiling']}", flush=True)
 
 
 if __name__ == "__main__":

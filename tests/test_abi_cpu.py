@@ -65,7 +65,7 @@ def test_valid_plan_and_sizes(L):
     assert st == L.LTM_ERR_WORKSPACE
     t = L.Tiling()
     assert L.lib().ltm_plan_get_tiling(h, 1, 0, ctypes.byref(t)) == 0
-    t.order = 64                                         # flags are bits 0..5
+    t.order = 128                                        # flags are bits 0..6
     assert L.lib().ltm_plan_set_tiling(h, 1, 0, ctypes.byref(t)) == L.LTM_ERR_INVALID
     t.order = 1
     t.splits = 1

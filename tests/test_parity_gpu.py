@@ -237,3 +237,29 @@ def test_differentiable_256_sampled_pixels(orc, ltm):
         assert np.count_nonzero(ref) > 100
         assert e < TOL
         off += npx
+
+
+def test_differentiable_256_full_at_tuned_tilings(orc, ltm):
+    # the 256^3 four-camera workload (2048^2 detectors, 128^2 lenslets, 2x1
+    # rays, 512 samples) in the tilings the benchmark times -- the committed
+    # tuned table, applied through the tuner's parity gate -- against the
+    # oracle on every pixel and every voxel: A x on the flame volume, A^T y on
+    # a seeded image of the same size
+    from paper_1812_03358_amd import autotune
+    cfg = W.config_differentiable()
+    g, cams = cfg["grid"], cfg["cameras"]
+    x = cfg["volume"]()
+    plan = ltm.Plan(g, cams)
+    xd = torch.from_numpy(x.reshape(-1)).cuda()
+    y = W.uniform_random(plan.n_meas, seed=44)
+    yd = torch.from_numpy(y).cuda()
+    res = autotune.autotune_plan(plan, xd, yd, reps=1, cache=autotune.TUNED_TABLE)
+    for r in res:
+        print("camera", r["camera"], "dir", r["direction"], r["tiling"], flush=True)
+    Ax = plan.project(xd).cpu().numpy()
+    Aty = plan.backproject(yd).cpu().numpy()
+    ref_Ax = orc.project(g, cams, x.astype(np.float64).reshape(-1))
+    ref_Aty = orc.backproject(g, cams, y.astype(np.float64))
+    e1, e2 = rel_l2(Ax, ref_Ax), rel_l2(Aty, ref_Aty)
+    print(f"differentiable_256 tuned: A {e1:.2e}  A^T {e2:.2e}", flush=True)
+    assert e1 < TOL and e2 < TOL
