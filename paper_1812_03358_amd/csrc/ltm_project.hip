@@ -826,7 +826,7 @@ __device__ void march_tile(const CamDev& c, int tile, const float* __restrict__ 
 }
 
 template <bool kAdj>
-__global__ __launch_bounds__(kThreads) void k_march(CamDev c, const float* __restrict__ in,
+__global__ __launch_bounds__(kThreads, 4) void k_march(CamDev c, const float* __restrict__ in,
                                                     float* __restrict__ yout,
                                                     double* __restrict__ xacc)
 {
@@ -840,7 +840,7 @@ __global__ __launch_bounds__(kThreads) void k_march(CamDev c, const float* __res
 // (every workgroup reaches the exit once the counter passes n_items).
 // Items are ordered by decreasing estimated cost.
 template <bool kAdj>
-__global__ __launch_bounds__(kThreads) void k_batch(const BatchCam* __restrict__ cams,
+__global__ __launch_bounds__(kThreads, 4) void k_batch(const BatchCam* __restrict__ cams,
                                                     const uint32_t* __restrict__ items,
                                                     uint32_t n_items,
                                                     unsigned int* __restrict__ counter)
