@@ -131,21 +131,34 @@ def solve_to(plan, y, x0=None, rho_target=1e-3, max_iter=5000, check_every=10, p
             "accepted": accepted, "alpha": alpha, "rho0": rho0}
 
 
-def compare(net, plan, n, seeds, rho_target=1e-3, max_iter=5000, check_every=10, log=None):
-    """Zero start vs warm start on held-out seeds."""
+def compare(net, plan, n, seeds, rho_target=1e-3, max_iter=5000, check_every=10, log=None,
+            workers=1):
+    """Zero start vs warm start on held-out seeds (volumes made by `workers`
+    host processes when workers > 1)."""
     rows = []
-    for seed in seeds:
-        x = torch.from_numpy(W.flame(n, seed).reshape(-1)).to(net.device)
-        y = plan.project(x).clone()
-        zero = solve_to(plan, y, None, rho_target, max_iter, check_every)
-        warm = solve_to(plan, y, None, rho_target, max_iter, check_every,
-                        prelude=lambda: infer(net, plan, y, n).contiguous())
-        x0 = infer(net, plan, y, n)
-        err0 = float(torch.linalg.norm(x0 - x) / torch.linalg.norm(x))
-        row = {"seed": seed, "zero": zero, "warm": warm, "net_rel_error": err0}
-        rows.append(row)
-        if log:
-            log(f"seed {seed}: zero {zero['iterations']} it {zero['seconds']:.2f}s rho {zero['rho']:.2e} | "
-                f"warm {warm['iterations']} it {warm['seconds']:.2f}s rho {warm['rho']:.2e} | "
-                f"network error {err0:.3f}")
+    stream = VolumeStream(n, seeds, workers) if workers > 1 else None
+    vols = stream if stream is not None else ((s, W.flame(n, s)) for s in seeds)
+    try:
+        for seed, vol in vols:
+            rows.append(_compare_one(net, plan, n, seed, vol, rho_target, max_iter, check_every, log))
+    finally:
+        if stream is not None:
+            stream.close()
     return rows
+
+
+def _compare_one(net, plan, n, seed, vol, rho_target, max_iter, check_every, log):
+    """One held-out volume: the zero-start and warm-start solves of its images."""
+    x = torch.from_numpy(vol.reshape(-1)).to(net.device)
+    y = plan.project(x).clone()
+    zero = solve_to(plan, y, None, rho_target, max_iter, check_every)
+    warm = solve_to(plan, y, None, rho_target, max_iter, check_every,
+                    prelude=lambda: infer(net, plan, y, n).contiguous())
+    x0 = infer(net, plan, y, n)
+    err0 = float(torch.linalg.norm(x0 - x) / torch.linalg.norm(x))
+    row = {"seed": seed, "zero": zero, "warm": warm, "net_rel_error": err0}
+    if log:
+        log(f"seed {seed}: zero {zero['iterations']} it {zero['seconds']:.2f}s rho {zero['rho']:.2e} | "
+            f"warm {warm['iterations']} it {warm['seconds']:.2f}s rho {warm['rho']:.2e} | "
+            f"network error {err0:.3f}")
+    return row

@@ -65,13 +65,14 @@ def _place(cam: dict, distance: float, phi_deg: float) -> dict:
 
 def single_lens_camera(det: int = 64, rays=(1, 1), samples: int = 64,
                        phi_deg: float = 0.0, det_v: int | None = None,
-                       distance: float | None = None) -> dict:
-    """Single-lens camera of the paper's simulated single-lens table."""
+                       distance: float | None = None, r_main: float = TL_R) -> dict:
+    """Single-lens camera of the paper's simulated single-lens table
+    (r_main: the main-lens aperture radius, the table's 5 mm by default)."""
     if distance is None:
         distance = TL_F * TL_D / (TL_D - TL_F)  # detector conjugate plane
     cam = dict(kind=SINGLE_LENS, det_nu=det, det_nv=det if det_v is None else det_v,
                mla_nu=0, mla_nv=0, rays_u=rays[0], rays_v=rays[1],
-               samples=samples, pixel_pitch=TL_PITCH, f_main=TL_F, r_main=TL_R,
+               samples=samples, pixel_pitch=TL_PITCH, f_main=TL_F, r_main=r_main,
                d_det=TL_D, d_mla=0.0, d_mla_det=0.0, f_mla=0.0, r_mla=0.0)
     return _place(cam, distance, phi_deg)
 

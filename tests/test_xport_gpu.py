@@ -67,6 +67,28 @@ def test_transport_matches_oracle(ltm, basis, dims, det, rays, dist):
     assert dot < dot_bar(x64, ref_Aty, y64, ref_Ax, stored=2)
 
 
+@pytest.mark.parametrize("basis", [0, 1])
+def test_wide_aperture_transport_matches_oracle(ltm, basis):
+    # r_main 15 mm (f/1): the defocus blur spans several pixels per slice
+    # (each angular cell's slice shift grows with the aperture)
+    dims = (20, 18, 16)
+    g = W.grid(dims, 1.0)
+    cam = W.single_lens_camera(200, (4, 4), 8, r_main=15.0)
+    x = W.flame(max(dims), seed=13)[:dims[2], :dims[1], :dims[0]]
+    y = W.uniform_random(200 * 200, seed=14)
+    op = ltm.Transport(g, cam, basis)
+    narrow = ltm.Transport(g, W.single_lens_camera(200, (4, 4), 8), basis)
+    Ax = op.project(_dev(x)).cpu().numpy()
+    assert rel_l2(narrow.project(_dev(x)).cpu().numpy(), Ax) > 1e-3
+    Aty = op.backproject(_dev(y)).cpu().numpy()
+    ref_Ax = OT.project(g, cam, x, basis)
+    ref_Aty = OT.backproject(g, cam, y, basis)
+    e1, e2 = rel_l2(Ax, ref_Ax), rel_l2(Aty, ref_Aty)
+    print(f"wide aperture basis={basis}: A {e1:.2e} A^T {e2:.2e} bands {op.bands()} "
+          f"(5 mm: {narrow.bands()})", flush=True)
+    assert e1 < 1e-5 and e2 < 1e-5
+
+
 def test_transport_entrywise_transpose(ltm):
     g = W.grid((6, 5, 4), 1.0)
     cam = W.single_lens_camera(24, (3, 3), 4, distance=300.0)
