@@ -54,6 +54,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a)
     const int cin = a.c0 + a.c1;
     const int taps = KS * KS * KS;
     const int vbase = (blockIdx.x * 4 + wave) * (16 * MT);
+    // this workgroup's output channels: tiles [blockIdx.y NT, blockIdx.y NT + NT)
+    const int c16 = blockIdx.y * NT * 16;
 
     int vz[MT], vy[MT], vx[MT];
     bool vin[MT];
@@ -96,7 +98,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a)
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 Frag B;
-                B.q = *reinterpret_cast<const uint4*>(a.wt + (size_t)(t * 16 + r) * a.Kp + kk);
+                B.q = *reinterpret_cast<const uint4*>(a.wt + (size_t)(c16 + t * 16 + r) * a.Kp + kk);
 #pragma unroll
                 for (int m = 0; m < MT; ++m)
                     acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[m].v, B.v, acc[m][t], 0, 0, 0);
@@ -133,7 +135,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a)
                 }
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
-                    B[u][t].q = *reinterpret_cast<const uint4*>(a.wt + (size_t)(t * 16 + r) * a.Kp + kk);
+                    B[u][t].q = *reinterpret_cast<const uint4*>(a.wt + (size_t)(c16 + t * 16 + r) * a.Kp + kk);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -153,7 +155,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvFwd a)
     for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const int co = t * 16 + r;
+            const int co = c16 + t * 16 + r;
             if (co >= a.cout) continue;
             const float b = a.bias ? a.bias[co] : 0.0f;
 #pragma unroll
@@ -199,8 +201,12 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(ConvFwd a)
     const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, z0 = blockIdx.z * kTZ;
     // stage the halo in 8-channel groups (16 bytes; c0 and c1 are multiples of 8)
     const int groups = cin >> 3;
+    // groups is a power of two for 8, 16, 32 and 64 channels: split i by shifts
+    const bool gpow2 = (groups & (groups - 1)) == 0;
+    const int lg = __ffs(groups) - 1;
     for (int i = threadIdx.x; i < kHX * kHY * kHZ * groups; i += 256) {
-        const int g = i % groups, vox = i / groups;
+        const int g = gpow2 ? (i & (groups - 1)) : i % groups;
+        const int vox = gpow2 ? (i >> lg) : i / groups;
         const int hx = vox % kHX, hy = (vox / kHX) % kHY, hz = vox / (kHX * kHY);
         const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
         const bool ok = (unsigned)x < (unsigned)a.W && (unsigned)y < (unsigned)a.H && (unsigned)z < (unsigned)a.D;
@@ -213,34 +219,74 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(ConvFwd a)
         *reinterpret_cast<uint4*>(hs + (size_t)vox * cin + ci) = ok ? q : uint4{0u, 0u, 0u, 0u};
     }
     (void)Din;
+    // per K-step and lane group: the halo offset (in u16) of the 8 channels
+    // [ci, ci + 8) of tap (dz, dy, dx), relative to the lane's output voxel;
+    // steps past the 27 taps (K padding, zero weights) point at offset 0 and
+    // their A fragment is zeroed below
+    const int nsteps = a.Kp >> 5;
+    int* koff = reinterpret_cast<int*>(hs + (size_t)kHX * kHY * kHZ * cin);
+    for (int i = threadIdx.x; i < nsteps * 4; i += 256) {
+        const int k = (i >> 2) * 32 + 8 * (i & 3);
+        const int tap = k / cin, ci = k - tap * cin;
+        int off = 0;
+        if (tap < 27) {
+            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            off = ((dz * kHY + dy) * kHX + dx) * cin + ci;
+        }
+        koff[i] = off;
+    }
     __syncthreads();
     f32x4 acc[kTZ][NT];
 #pragma unroll
     for (int m = 0; m < kTZ; ++m)
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int nsteps = a.Kp >> 5;
-    for (int ks = 0; ks < nsteps; ++ks) {
-        const int k = ks * 32 + 8 * kg;
-        const int tap = k / cin, ci = k - tap * cin;
-        const bool tapok = tap < 27;
-        const int tp = tapok ? tap : 0;
-        const int dz = tp / 9 - 1, dy = (tp / 3) % 3 - 1, dx = tp % 3 - 1;
-        Frag B[NT];
+    // the lane's output voxel (x0 + r, y0 + wave, z0 + m) sits at halo
+    // (1 + r, 1 + wave, 1 + m)
+    const u16* abase = hs + (size_t)(((1 * kHY + 1 + wave) * kHX) + 1 + r) * cin;
+    const size_t mstride = (size_t)kHY * kHX * cin;
+    const u16* bbase = a.wt + (size_t)r * a.Kp + 8 * kg;
+    // two steps per trip with alternating operand buffers: the B fragments
+    // and the offset of the next step are loaded while a step runs its MFMAs;
+    // only the last step can hold K padding, so it alone (peeled) selects
+    auto loadB = [&](Frag (&b)[NT], int ks) {
 #pragma unroll
         for (int t = 0; t < NT; ++t)
-            B[t].q = *reinterpret_cast<const uint4*>(a.wt + (size_t)(t * 16 + r) * a.Kp + k);
-        const int hxy = ((1 + wave + dy) * kHX + (1 + r + dx));
+            b[t].q = *reinterpret_cast<const uint4*>(bbase + (size_t)t * 16 * a.Kp + ks * 32);
+    };
+    auto mma = [&](const Frag (&b)[NT], int off, bool pad_step, int ks) {
+        const bool ok = !pad_step || (ks * 32 + 8 * kg) < 27 * cin;
+        Frag A[kTZ];
 #pragma unroll
         for (int m = 0; m < kTZ; ++m) {
-            Frag A;
-            const uint4 q = *reinterpret_cast<const uint4*>(
-                hs + (size_t)(((1 + m + dz) * kHY * kHX) + hxy) * cin + ci);
-            A.q = tapok ? q : uint4{0u, 0u, 0u, 0u};
+            A[m].q = *reinterpret_cast<const uint4*>(abase + m * mstride + off);
+            if (pad_step) A[m].q = ok ? A[m].q : uint4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int m = 0; m < kTZ; ++m)
 #pragma unroll
             for (int t = 0; t < NT; ++t)
-                acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.v, B[t].v, acc[m][t], 0, 0, 0);
-        }
+                acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[m].v, b[t].v, acc[m][t], 0, 0, 0);
+    };
+    Frag B0[NT], B1[NT];
+    int off0 = koff[kg], off1 = 0;
+    loadB(B0, 0);
+    int ks = 0;
+    for (; ks + 2 < nsteps; ks += 2) {
+        loadB(B1, ks + 1);
+        off1 = koff[(ks + 1) * 4 + kg];
+        mma(B0, off0, false, ks);
+        loadB(B0, ks + 2);
+        off0 = koff[(ks + 2) * 4 + kg];
+        mma(B1, off1, false, ks + 1);
+    }
+    if (ks + 1 < nsteps) {
+        loadB(B1, ks + 1);
+        off1 = koff[(ks + 1) * 4 + kg];
+        mma(B0, off0, false, ks);
+        mma(B1, off1, true, ks + 1);
+    } else if (ks < nsteps) {
+        mma(B0, off0, true, ks);
     }
     // epilogue: output row 4 kg + i of tile m is voxel (x0 + 4 kg + i, y0 + wave, z0 + m)
     const int y = y0 + wave;
@@ -272,6 +318,75 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(ConvFwd a)
                 }
             }
         }
+}
+
+// 3x3x3 convolution of a single input channel (the network's input layer),
+// up to 16 output channels: 27 MACs per output channel, so FP32 FMAs on the
+// BF16 values (their products are exact in FP32) instead of MFMAs whose K
+// values would each be a separately gathered tap.  A workgroup stages the
+// 18 x 6 x 6 input halo of a 16 x 4 x 4 output block in LDS; each thread
+// computes one output voxel's channels.  The weights are the same for every
+// lane (read with uniform addresses, so they arrive through scalar loads).
+__global__ __launch_bounds__(256) void k_conv_fwd_c1(ConvFwd a)
+{
+    __shared__ float halo[6][6][18];
+    const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 4, z0 = blockIdx.z * 4;
+    const int Hin = a.H >> a.up, Win = a.W >> a.up;
+    for (int i = threadIdx.x; i < 18 * 6 * 6; i += 256) {
+        const int hx = i % 18, hy = (i / 18) % 6, hz = i / 108;
+        const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+        const bool ok = (unsigned)x < (unsigned)a.W && (unsigned)y < (unsigned)a.H && (unsigned)z < (unsigned)a.D;
+        halo[hz][hy][hx] =
+            ok ? bf2f(a.in0[((size_t)(z >> a.up) * Hin + (y >> a.up)) * Win + (x >> a.up)]) : 0.0f;
+    }
+    __syncthreads();
+    const int tx = threadIdx.x & 15, ty = (threadIdx.x >> 4) & 3, tz = threadIdx.x >> 6;
+    const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
+    if (x >= a.W || y >= a.H || z >= a.D) return;
+    float v[27];
+#pragma unroll
+    for (int t = 0; t < 27; ++t) v[t] = halo[tz + t / 9][ty + (t / 3) % 3][tx + t % 3];
+    const size_t vox = ((size_t)z * a.H + y) * a.W + x;
+    float out[16];
+#pragma unroll
+    for (int co = 0; co < 16; ++co) {
+        if (co >= a.cout) {
+            out[co] = 0.0f;
+            continue;
+        }
+        const u16* wr = a.wt + (size_t)co * a.Kp;
+        float acc = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 27; ++t) acc = fmaf(bf2f(wr[t]), v[t], acc);
+        acc += a.bias ? a.bias[co] : 0.0f;
+        out[co] = a.relu ? fmaxf(acc, 0.0f) : acc;
+    }
+    if (!a.out_f32 && a.split == 16 && a.cout == 16) {
+        // one voxel's 16 BF16 channels: two 16-byte stores
+        Frag lo, hi;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            lo.h[j] = f2bf(out[j]);
+            hi.h[j] = f2bf(out[8 + j]);
+        }
+        uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<u16*>(a.out) + vox * 16);
+        dst[0] = lo.q;
+        dst[1] = hi.q;
+        return;
+    }
+#pragma unroll
+    for (int co = 0; co < 16; ++co) {
+        if (co >= a.cout) break;
+        if (co < a.split) {
+            const size_t o = vox * a.split + co;
+            if (a.out_f32) reinterpret_cast<float*>(a.out)[o] = out[co];
+            else reinterpret_cast<u16*>(a.out)[o] = f2bf(out[co]);
+        } else {
+            const size_t o = vox * (a.cout - a.split) + (co - a.split);
+            if (a.out_f32) reinterpret_cast<float*>(a.out2)[o] = out[co];
+            else reinterpret_cast<u16*>(a.out2)[o] = f2bf(out[co]);
+        }
+    }
 }
 
 // ---------------------------------------------------------------- wgrad
@@ -637,15 +752,26 @@ unsigned nblocks(size_t n)
     return (unsigned)(b > 16384 ? 16384 : (b ? b : 1));
 }
 
+template <int KS, bool CIN1, int NT, int MT>
+hipError_t conv_launch(const ConvFwd& a, int groups, hipStream_t s)
+{
+    const int V = a.D * a.H * a.W;
+    const int per_block = 4 * 16 * MT;
+    hipLaunchKernelGGL((k_conv_fwd<KS, CIN1, NT, MT>), dim3((V + per_block - 1) / per_block, groups), dim3(256),
+                       0, s, a);
+    return hipGetLastError();
+}
+
 template <int KS, bool CIN1, int NT>
 hipError_t conv_mt(const ConvFwd& a, hipStream_t s)
 {
     constexpr int MT = NT >= 8 ? 1 : (NT >= 4 ? 2 : 4);
     const int V = a.D * a.H * a.W;
-    const int per_block = 4 * 16 * MT;
-    hipLaunchKernelGGL((k_conv_fwd<KS, CIN1, NT, MT>), dim3((V + per_block - 1) / per_block), dim3(256), 0,
-                       s, a);
-    return hipGetLastError();
+    // small grids (16^3, 32^3): one 16-channel tile and 16 voxels per wave, the
+    // channel tiles spread over blockIdx.y, so enough waves run to hide latency
+    if (NT > 1 && (long long)(V + 4 * 16 * MT - 1) / (4 * 16 * MT) < 256)
+        return conv_launch<KS, CIN1, 1, 1>(a, NT, s);
+    return conv_launch<KS, CIN1, NT, MT>(a, 1, s);
 }
 
 template <int KS, bool CIN1>
@@ -669,11 +795,21 @@ hipError_t nn_conv_fwd(const ConvFwd& a, int ks, hipStream_t s)
     const int cin = a.c0 + a.c1;
     const bool cin1 = cin == 1;
     if (ks == 3 && cin >= 8 && cin <= 64 && cin % 8 == 0) {
-        // 4 output planes per workgroup up to 32 channels (41 KiB halo), 2 up to 64 (55 KiB)
-        const int tz = cin <= 32 ? 4 : 2;
+        // 8 output planes per workgroup up to 16 channels (35 KiB halo), 4 up to 32
+        // (41 KiB), 2 up to 64 (55 KiB)
+        const int tz = (cin <= 16 && ntp <= 4) ? 8 : (cin <= 32 ? 4 : 2);
         const dim3 g((a.W + kTX - 1) / kTX, (a.H + kTY - 1) / kTY, (a.D + tz - 1) / tz);
-        const size_t lds = (size_t)kHX * kHY * (tz + 2) * cin * sizeof(unsigned short);
-        if (tz == 4) {
+        // the halo, then the per-step offset table (nsteps x 4 ints)
+        const size_t lds = (size_t)kHX * kHY * (tz + 2) * cin * sizeof(unsigned short) +
+                           (size_t)(a.Kp / 32) * 4 * sizeof(int);
+        if (tz == 8) {
+            switch (ntp) {
+            case 1: hipLaunchKernelGGL((k_conv_fwd_lds<1, 8>), g, dim3(256), lds, s, a); break;
+            case 2: hipLaunchKernelGGL((k_conv_fwd_lds<2, 8>), g, dim3(256), lds, s, a); break;
+            case 4: hipLaunchKernelGGL((k_conv_fwd_lds<4, 8>), g, dim3(256), lds, s, a); break;
+            default: return hipErrorInvalidValue;   // tz = 8 is chosen only for ntp <= 4
+            }
+        } else if (tz == 4) {
             switch (ntp) {
             case 1: hipLaunchKernelGGL((k_conv_fwd_lds<1, 4>), g, dim3(256), lds, s, a); break;
             case 2: hipLaunchKernelGGL((k_conv_fwd_lds<2, 4>), g, dim3(256), lds, s, a); break;
@@ -688,6 +824,11 @@ hipError_t nn_conv_fwd(const ConvFwd& a, int ks, hipStream_t s)
             default: hipLaunchKernelGGL((k_conv_fwd_lds<8, 2>), g, dim3(256), lds, s, a); break;
             }
         }
+        return hipGetLastError();
+    }
+    if (ks == 3 && cin1 && a.c1 == 0 && a.cout <= 16) {
+        const dim3 g((a.W + 15) / 16, (a.H + 3) / 4, (a.D + 3) / 4);
+        hipLaunchKernelGGL(k_conv_fwd_c1, g, dim3(256), 0, s, a);
         return hipGetLastError();
     }
     if (ks == 3) return cin1 ? conv_nt<3, true>(a, ntp, s) : conv_nt<3, false>(a, ntp, s);

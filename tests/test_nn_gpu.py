@@ -45,6 +45,8 @@ CASES = [
     (8, 6, 8, 32, 0, 16, 3, 1),
     (6, 5, 7, 16, 0, 1, 1, 0),
     (6, 6, 6, 24, 0, 40, 3, 0),
+    # 8 output planes per workgroup (at most 16 input channels) over a ragged depth
+    (10, 6, 12, 8, 8, 32, 3, 0),
     # power-of-two rows (the shift-indexed weight-gradient kernel): a skip
     # concatenation, an upsampled input, 128 output channels
     (4, 8, 16, 32, 32, 32, 3, 0),
