@@ -126,6 +126,55 @@ def test_tilings_agree(orc, ltm):
         assert rel_l2(Aty, base_Aty) < 1e-6, v
 
 
+def test_zero_inputs_give_exact_zeros(ltm):
+    # A 0 = 0 and A^T 0 = 0 exactly (no stale accumulator, no uninitialized
+    # output), after a nonzero call on the same plan
+    g = W.grid((20, 24, 18), 6.0)
+    cams = [W.plenoptic_camera(96, 6, (2, 2), 37, phi_deg=30.0)]
+    _run(ltm, g, cams, W.flame(24, seed=7)[:18, :24, :20], W.uniform_random(96 * 96, seed=32))
+    Ax, Aty, _ = _run(ltm, g, cams, np.zeros((18, 24, 20), np.float32), np.zeros(96 * 96, np.float32))
+    assert np.all(Ax == 0) and np.all(Aty == 0)
+
+
+@pytest.mark.parametrize("kind", ["plenoptic", "single"])
+def test_impulses_match_oracle(orc, ltm, kind):
+    # one bright voxel (the operator's column) and one bright pixel (its row)
+    g = W.grid((16, 14, 12), 7.0)
+    cams = ([W.plenoptic_camera(64, 4, (2, 2), 29, phi_deg=20.0)] if kind == "plenoptic" else
+            [W.single_lens_camera(40, (3, 3), 23, phi_deg=-25.0, distance=400.0)])
+    npx = W.n_pixels(cams[0])
+    x = np.zeros((12, 14, 16), np.float32)
+    x[6, 7, 8] = 1.0
+    y = np.zeros(npx, np.float32)
+    ref_full = orc.project(g, cams, np.ones(g["nx"] * g["ny"] * g["nz"]))
+    y[int(np.argmax(ref_full))] = 1.0            # a pixel that sees the grid
+    Ax, Aty, _ = _run(ltm, g, cams, x, y)
+    ref_Ax = orc.project(g, cams, x.astype(np.float64).reshape(-1))
+    ref_Aty = orc.backproject(g, cams, y.astype(np.float64))
+    assert np.linalg.norm(ref_Ax) > 0 and np.linalg.norm(ref_Aty) > 0
+    e1, e2 = rel_l2(Ax, ref_Ax), rel_l2(Aty, ref_Aty)
+    print(f"impulse {kind}: A {e1:.2e} A^T {e2:.2e}", flush=True)
+    assert e1 < TOL and e2 < TOL
+    # supports agree exactly: the GPU touches no voxel or pixel the oracle does not
+    assert np.array_equal(Ax != 0, ref_Ax != 0)
+    assert np.array_equal(Aty != 0, ref_Aty != 0)
+
+
+def test_degenerate_sizes_match_oracle(orc, ltm):
+    # the smallest grid (2 x 2 x 2), one ray and one sample per pixel, a
+    # detector of one row
+    g = W.grid(2, 20.0)
+    cams = [W.single_lens_camera(24, (1, 1), 1, det_v=1, distance=300.0),
+            W.plenoptic_camera(32, 2, (1, 1), 1, phi_deg=90.0)]
+    x = W.uniform_random((2, 2, 2), seed=51)
+    y = W.uniform_random(24 + 32 * 32, seed=52)
+    Ax, Aty, _ = _run(ltm, g, cams, x, y)
+    ref_Ax = orc.project(g, cams, x.astype(np.float64).reshape(-1))
+    ref_Aty = orc.backproject(g, cams, y.astype(np.float64))
+    assert np.linalg.norm(ref_Ax) > 0
+    assert rel_l2(Ax, ref_Ax) < TOL and rel_l2(Aty, ref_Aty) < TOL
+
+
 def test_camera_behind_volume_sees_nothing(ltm):
     g = W.grid(8, 1.0)
     cam = W.single_lens_camera(16, (1, 1), 8)
