@@ -772,7 +772,19 @@ __device__ void march_tile(const CamDev& c, int tile, const float* __restrict__ 
             }
             __syncthreads();
         }
-        for (int e = threadIdx.x; e < nrays; e += kThreads) {
+        // whole passes give each lane one ray.  In the forward, a last,
+        // partial pass of `left` rays splits each of them into kThreads / left
+        // pieces of its sample range, so all waves share it instead of a few
+        // lanes running whole rays (the pieces' sums meet in the pixel's FP64
+        // LDS word).  The adjoint keeps whole rays: its plane window costs a
+        // set-up and up to 8 closing atomics per piece, too much for pieces of
+        // a few samples (measured slower).
+        for (int e0 = 0; e0 < nrays; e0 += kThreads) {
+            const int left = nrays - e0;
+            const int parts = (kAdj || left >= kThreads) ? 1 : kThreads / left;
+            if ((int)threadIdx.x >= parts * min(left, kThreads)) continue;
+            const int e = parts == 1 ? e0 + (int)threadIdx.x : e0 + (int)threadIdx.x % left;
+            const int part = parts == 1 ? 0 : (int)threadIdx.x / left;
             const uint32_t id = m.list[e];
             const int item = (int)(id & 0xffffu), rr = (int)(id >> 16);
             int iu, iv;
@@ -780,8 +792,14 @@ __device__ void march_tile(const CamDev& c, int tile, const float* __restrict__ 
             const int rv = rr / c.ru, ru = rr - rv * c.ru;
             Ray r;
             make_ray(c, iu, iv, ru, rv, r);
-            const int m0 = sample_bound(r, za, c.S);
-            const int m1 = last ? c.S : sample_bound(r, zb, c.S);
+            int m0 = sample_bound(r, za, c.S);
+            int m1 = last ? c.S : sample_bound(r, zb, c.S);
+            if (parts > 1 && m1 > m0) {
+                const int len = m1 - m0;
+                const int a = m0 + (len * part) / parts, b = m0 + (len * (part + 1)) / parts;
+                m0 = a;
+                m1 = b;
+            }
             if (m0 >= m1) continue;
             const March mr = march_of(r);
             if (!kAdj) {
