@@ -778,7 +778,9 @@ __device__ void march_tile(const CamDev& c, int tile, const float* __restrict__ 
         // lanes running whole rays (the pieces' sums meet in the pixel's FP64
         // LDS word).  The adjoint keeps whole rays: its plane window costs a
         // set-up and up to 8 closing atomics per piece, too much for pieces of
-        // a few samples (measured slower).
+        // a few samples (measured slower), and 4 pieces of a last pass of at
+        // most 64 rays, one per wave, measured no faster: other workgroups
+        // fill the idle SIMDs.
         for (int e0 = 0; e0 < nrays; e0 += kThreads) {
             const int left = nrays - e0;
             const int parts = (kAdj || left >= kThreads) ? 1 : kThreads / left;
