@@ -36,6 +36,7 @@ __device__ __forceinline__ u16 f2bf(float f)
 union Frag {
     bf16x8 v;
     uint4 q;
+    unsigned int w[4];
     u16 h[8];
 };
 
@@ -544,6 +545,209 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_pow2(ConvWgrad a, int lw, in
     }
 }
 
+// Weight gradient of a 3x3x3 convolution for rows whose width is a multiple
+// of XC (32, 64 or 128) voxels and Cin, Cout multiples of 16.  A tap's x shift
+// is moved from the input onto dY: sum_x dY[x] X[x + dx] = sum_x' dY[x' - dx]
+// X[x'], each input position x' paired by the unit that holds it.  A unit is
+// XC voxels (chunk) of one output row (z, y).  Per unit a workgroup holds in
+// LDS the 9 input rows (z + dz, y + dy) the taps reach, at the unit's own x
+// range and for one 16-channel input tile, and the unit's dY for one
+// 16-channel output tile in three copies shifted by dx = -1, 0, 1 (zeros
+// outside the grid; upsampling and concatenation resolved while staging).
+// Both are stored transposed, [channel][x], so every MFMA operand (8
+// consecutive voxels of one channel) is one aligned 16-byte LDS read, and one
+// input fragment feeds the three taps that differ only in dx.  Units run over
+// (z, chunk, y) with y fastest: the input rows sit in a ring of 3 x 3 slots
+// (slot (dz, y' mod 3)), so a unit after its y - 1 neighbour loads only the 3
+// rows y + 1; and the next unit's loads are issued into registers before the
+// current unit's MFMAs.  A workgroup owns (output tile, input tile, a
+// contiguous share of the units); wave w holds the 9 k-tiles of dy = w - 1 in
+// registers over its share and adds them into dw once.
+template <int XC>
+struct WgradStage {
+    static constexpr int NX8 = XC / 8;
+    static constexpr int NIT = (9 * 2 * NX8 + 191) / 192;     // input items per thread (a full stage)
+    static constexpr int NDI = (2 * (XC + 2) + 191) / 192;    // dY items per thread
+    Frag q[NIT][8];
+    Frag f[NDI];
+};
+
+template <int XC>
+__device__ __forceinline__ void wgrad_load(const ConvWgrad& a, int cit, int cot, int z, int y, int x0, bool full,
+                                           WgradStage<XC>& st)
+{
+    constexpr int NX8 = XC / 8;
+    const int nitems = (full ? 9 : 3) * 2 * NX8;
+    const int Hin = a.H >> a.up, Win = a.W >> a.up;
+#pragma unroll
+    for (int it = 0; it < WgradStage<XC>::NIT; ++it) {
+        const int i = (int)threadIdx.x + 192 * it;
+        const int x8 = i % NX8, g = (i / NX8) & 1, rs = i / (2 * NX8);
+        const int dzi = full ? rs / 3 : rs, k = full ? rs % 3 : 2;
+        const int zz = z + dzi - 1, yy = y + k - 1;
+        const int ci = cit * 16 + g * 8;
+        const int xb = x0 + x8 * 8;
+        if (i < nitems && (unsigned)zz < (unsigned)a.D && (unsigned)yy < (unsigned)a.H) {
+            if (ci < a.c0) {
+                const u16* src = a.in0 + ((size_t)(zz >> a.up) * Hin + (yy >> a.up)) * Win * a.c0 + ci;
+#pragma unroll
+                for (int jx = 0; jx < 8; ++jx)
+                    st.q[it][jx].q = *reinterpret_cast<const uint4*>(src + (size_t)((xb + jx) >> a.up) * a.c0);
+            } else {
+                const u16* src = a.in1 + ((size_t)zz * a.H + yy) * a.W * a.c1 + (ci - a.c0);
+#pragma unroll
+                for (int jx = 0; jx < 8; ++jx)
+                    st.q[it][jx].q = *reinterpret_cast<const uint4*>(src + (size_t)(xb + jx) * a.c1);
+            }
+        } else {
+#pragma unroll
+            for (int jx = 0; jx < 8; ++jx) st.q[it][jx].q = uint4{0u, 0u, 0u, 0u};
+        }
+    }
+    const size_t rowbase = ((size_t)z * a.H + y) * a.W;
+#pragma unroll
+    for (int it = 0; it < WgradStage<XC>::NDI; ++it) {
+        const int i = (int)threadIdx.x + 192 * it;
+        const int h = i >> 1, half = i & 1;
+        const int x = x0 - 1 + h;
+        st.f[it].q = (i < 2 * (XC + 2) && (unsigned)x < (unsigned)a.W)
+            ? *reinterpret_cast<const uint4*>(a.dy + (rowbase + x) * a.cout + cot * 16 + half * 8)
+            : uint4{0u, 0u, 0u, 0u};
+    }
+}
+
+template <int XC>
+__device__ __forceinline__ void wgrad_store(int y, bool full, const WgradStage<XC>& st, u16* xs, u16* dys)
+{
+    constexpr int NX8 = XC / 8, XS = XC + 8;
+    const int nitems = (full ? 9 : 3) * 2 * NX8;
+#pragma unroll
+    for (int it = 0; it < WgradStage<XC>::NIT; ++it) {
+        const int i = (int)threadIdx.x + 192 * it;
+        if (i >= nitems) continue;
+        const int x8 = i % NX8, g = (i / NX8) & 1, rs = i / (2 * NX8);
+        const int dzi = full ? rs / 3 : rs, k = full ? rs % 3 : 2;
+        const int slot = dzi * 3 + (y + k + 2) % 3;               // input row y + k - 1 -> slot (dz, y' mod 3)
+        u16* dst = xs + (slot * 16 + g * 8) * XS + x8 * 8;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            // channel j of voxels 2m, 2m + 1 -> one dword (low, high half)
+            const unsigned sel = (j & 1) ? 0x07060302u : 0x05040100u;
+            uint4 o;
+            o.x = __builtin_amdgcn_perm(st.q[it][1].w[j >> 1], st.q[it][0].w[j >> 1], sel);
+            o.y = __builtin_amdgcn_perm(st.q[it][3].w[j >> 1], st.q[it][2].w[j >> 1], sel);
+            o.z = __builtin_amdgcn_perm(st.q[it][5].w[j >> 1], st.q[it][4].w[j >> 1], sel);
+            o.w = __builtin_amdgcn_perm(st.q[it][7].w[j >> 1], st.q[it][6].w[j >> 1], sel);
+            *reinterpret_cast<uint4*>(dst + j * XS) = o;
+        }
+    }
+    // dY halo x0 - 1 + h: copy d (dx = d - 1) holds dY[x0 + i - dx] at i = h + d - 2
+#pragma unroll
+    for (int it = 0; it < WgradStage<XC>::NDI; ++it) {
+        const int i = (int)threadIdx.x + 192 * it;
+        if (i >= 2 * (XC + 2)) continue;
+        const int h = i >> 1, half = i & 1;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int ix = h + d - 2;
+            if ((unsigned)ix < (unsigned)XC) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) dys[(d * 16 + half * 8 + j) * XS + ix] = st.f[it].h[j];
+            }
+        }
+    }
+}
+
+template <int XC>
+__global__ __launch_bounds__(192) void k_conv_wgrad_rows(ConvWgrad a, int nshare)
+{
+    constexpr int XS = XC + 8;                   // LDS row stride (elements), padded against bank conflicts
+    extern __shared__ uint4 sm4[];
+    u16* xs = reinterpret_cast<u16*>(sm4);       // [9 slots][16 channels][XS]
+    u16* dys = xs + 9 * 16 * XS;                 // [3 shifts][16 channels][XS]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, kg = lane >> 4;
+    const int n_co = a.cout >> 4;
+    const int cot = blockIdx.x % n_co, cit = blockIdx.x / n_co;
+    const int cin = a.c0 + a.c1;
+    const int chunks = a.W / XC;
+    const int nunits = a.D * chunks * a.H;
+    const int u0 = (int)(((long long)nunits * blockIdx.y) / nshare);
+    const int u1 = (int)(((long long)nunits * (blockIdx.y + 1)) / nshare);
+    f32x4 acc[3][3];
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) acc[s][d] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // unit -> (z, chunk, y), y fastest
+    auto coords = [&](int unit, int& z, int& y, int& x0) {
+        const int zc = unit / a.H;
+        y = unit - zc * a.H;
+        z = zc / chunks;
+        x0 = (zc - z * chunks) * XC;
+    };
+    WgradStage<XC> st;
+    int z, y, x0;
+    if (u0 < u1) {
+        coords(u0, z, y, x0);
+        wgrad_load<XC>(a, cit, cot, z, y, x0, true, st);
+    }
+    for (int unit = u0; unit < u1; ++unit) {
+        const bool full = unit == u0 || y == 0;
+        const int ycur = y;
+        __syncthreads();   // the previous unit's fragments are read
+        wgrad_store<XC>(ycur, full, st, xs, dys);
+        __syncthreads();
+        if (unit + 1 < u1) {
+            coords(unit + 1, z, y, x0);
+            wgrad_load<XC>(a, cit, cot, z, y, x0, y == 0, st);
+        }
+        // wave w: dy = w - 1, input row y' = ycur + w - 1 in slot (s, y' mod 3)
+        const int ks = (ycur + wave + 2) % 3;
+#pragma unroll
+        for (int gv = 0; gv < XC; gv += 32) {
+            Frag A[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                A[d].q = *reinterpret_cast<const uint4*>(dys + (d * 16 + r) * XS + gv + 8 * kg);
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                Frag B;
+                B.q = *reinterpret_cast<const uint4*>(xs + ((s * 3 + ks) * 16 + r) * XS + gv + 8 * kg);
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    acc[s][d] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[d].v, B.v, acc[s][d], 0, 0, 0);
+            }
+        }
+    }
+    // D[4 kg + i][r]: output channel cot 16 + 4 kg + i, input channel
+    // cit 16 + r of tap (dz = s - 1, dy = wave - 1, dx = d - 1)
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int k = ((s * 3 + wave) * 3 + d) * cin + cit * 16 + r;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int c = cot * 16 + 4 * kg + i;
+                if (acc[s][d][i] != 0.0f) unsafeAtomicAdd(&a.dw[(size_t)c * a.K + k], acc[s][d][i]);
+            }
+        }
+}
+
+template <int XC>
+hipError_t wgrad_rows(const ConvWgrad& a, hipStream_t s)
+{
+    const int tiles = (a.cout / 16) * ((a.c0 + a.c1) / 16);
+    const int units = a.D * a.H * (a.W / XC);
+    // shares of the units per (output tile, input tile) until ~512 workgroups
+    // run (two per CU); each share adds its partial sums into dw
+    const int shares = std::max(1, std::min(units, 512 / tiles));
+    const size_t lds = (size_t)12 * 16 * (XC + 8) * sizeof(u16);
+    hipLaunchKernelGGL((k_conv_wgrad_rows<XC>), dim3(tiles, shares), dim3(192), lds, s, a, shares);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- elementwise
 // Pack FP32 master weights [Cout][K] into the BF16 forward layout
 // [NT*16][Kp] and the input-gradient layout [Cin_pad][Kp'] (flipped taps,
@@ -654,6 +858,62 @@ __global__ void k_relu_mask_pc(const float* __restrict__ dout, const u16* __rest
     for (int o = 32; o >= C && o > 0; o >>= 1) part += __shfl_xor(part, o);
     const int lane = threadIdx.x & 63;
     if (lane < C && part != 0.0f) atomicAdd(&sb[threadIdx.x % C], part);
+    __syncthreads();
+    if (dbias)
+        for (int c = threadIdx.x; c < C; c += blockDim.x)
+            if (sb[c] != 0.0f) unsafeAtomicAdd(&dbias[c], sb[c]);
+}
+
+// k_relu_mask_pc over 8 consecutive elements per thread and step (16-byte
+// loads and stores).  C divides 2048, so a thread's 8 elements keep their
+// channels (8 t + j) mod C through the grid-stride loop: the 8 sums stay in
+// registers, lanes holding the same channels are combined with wave
+// shuffles, and the rest reach LDS once per wave.
+__global__ __launch_bounds__(256) void k_relu_mask_v8(const float* __restrict__ dout, const u16* __restrict__ out,
+                                                      int relu, u16* __restrict__ g, float* __restrict__ dbias,
+                                                      size_t n8, int C)
+{
+    extern __shared__ float sb[];
+    for (int c = threadIdx.x; c < C; c += blockDim.x) sb[c] = 0.0f;
+    __syncthreads();
+    float part[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (size_t i = t0; i < n8; i += (size_t)gridDim.x * blockDim.x) {
+        const float4 d0 = reinterpret_cast<const float4*>(dout)[2 * i];
+        const float4 d1 = reinterpret_cast<const float4*>(dout)[2 * i + 1];
+        float v[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+        if (relu) {
+            Frag o;
+            o.q = reinterpret_cast<const uint4*>(out)[i];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (!(bf2f(o.h[j]) > 0.0f)) v[j] = 0.0f;
+        }
+        Frag b;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            b.h[j] = f2bf(v[j]);
+            part[j] += bf2f(b.h[j]);
+        }
+        reinterpret_cast<uint4*>(g)[i] = b.q;
+    }
+    // C < 8: element j of a thread has channel j mod C
+    if (C <= 4)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) part[j] += part[j + 4];
+    if (C <= 2)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) part[j] += part[j + 2];
+    if (C == 1) part[0] += part[1];
+    // lanes l and l ^ o hold the same channels when C divides 8 o
+    for (int o = 32; o >= 1 && 8 * o >= C; o >>= 1)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) part[j] += __shfl_xor(part[j], o);
+    const int lane = threadIdx.x & 63;
+    if (lane < (C >= 8 ? C / 8 : 1))
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (j < C && part[j] != 0.0f) atomicAdd(&sb[(int)((8 * t0 + j) % (size_t)C)], part[j]);
     __syncthreads();
     if (dbias)
         for (int c = threadIdx.x; c < C; c += blockDim.x)
@@ -837,6 +1097,14 @@ hipError_t nn_conv_fwd(const ConvFwd& a, int ks, hipStream_t s)
 
 hipError_t nn_conv_wgrad(const ConvWgrad& a, int ks, hipStream_t s)
 {
+    const int cin = a.c0 + a.c1;
+    const int xc = a.W % 128 == 0 ? 128 : a.W % 64 == 0 ? 64 : a.W % 32 == 0 ? 32 : 0;
+    if (ks == 3 && xc && cin % 16 == 0 && a.c0 % 8 == 0 && a.cout % 16 == 0 && a.K == 27 * cin &&
+        (!a.up || (a.W % 2 == 0 && a.H % 2 == 0 && a.D % 2 == 0))) {
+        if (xc == 128) return wgrad_rows<128>(a, s);
+        if (xc == 64) return wgrad_rows<64>(a, s);
+        return wgrad_rows<32>(a, s);
+    }
     auto lg2 = [](int n) { int l = 0; while ((1 << l) < n) ++l; return (1 << l) == n ? l : -1; };
     const int lw = lg2(a.W), lh = lg2(a.H);
     if (ks == 3 && lw >= 3 && lh >= 0 && (a.W * a.H) % 32 == 0 && a.cout % 16 == 0 &&
@@ -900,8 +1168,16 @@ hipError_t nn_relu_mask(const float* dout, const unsigned short* out, int relu, 
 {
     // at most 1024 workgroups: each adds C partial sums into dbias with
     // global atomics, which contend on the C addresses
+    const bool pow2 = C >= 1 && (C & (C - 1)) == 0;
+    const bool aligned = ((reinterpret_cast<uintptr_t>(dout) | reinterpret_cast<uintptr_t>(out) |
+                           reinterpret_cast<uintptr_t>(g)) & 15) == 0;
+    if (pow2 && C <= 2048 && n % 8 == 0 && aligned) {   // C divides the grid stride in elements (2048 k)
+        hipLaunchKernelGGL(k_relu_mask_v8, dim3(std::min(nblocks(n / 8), 1024u)), dim3(256), C * sizeof(float), s,
+                           dout, out, relu, g, dbias, n / 8, C);
+        return hipGetLastError();
+    }
     const dim3 grid(std::min(nblocks(n), 1024u));
-    if (C >= 1 && C <= 256 && (C & (C - 1)) == 0)   // C divides the grid stride (a multiple of 256)
+    if (pow2 && C <= 256)   // C divides the grid stride (a multiple of 256)
         hipLaunchKernelGGL(k_relu_mask_pc, grid, dim3(256), C * sizeof(float), s, dout, out, relu, g, dbias, n, C);
     else
         hipLaunchKernelGGL(k_relu_mask, grid, dim3(256), C * sizeof(float), s, dout, out, relu, g, dbias, n, C);

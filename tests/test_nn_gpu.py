@@ -47,6 +47,15 @@ CASES = [
     (6, 6, 6, 24, 0, 40, 3, 0),
     # 8 output planes per workgroup (at most 16 input channels) over a ragged depth
     (10, 6, 12, 8, 8, 32, 3, 0),
+    # row-staged weight gradient (rows of 128, 64, 32 voxels): plain,
+    # concatenated (also inside a 16-channel input tile), upsampled, 3 x 3
+    # (output, input) channel tiles
+    (2, 3, 128, 16, 0, 16, 3, 0),
+    (3, 2, 128, 8, 8, 32, 3, 0),
+    (2, 3, 32, 64, 0, 32, 3, 0),
+    (4, 2, 64, 32, 0, 16, 3, 1),
+    (3, 2, 64, 24, 8, 16, 3, 0),
+    (2, 2, 32, 32, 16, 48, 3, 1),
     # power-of-two rows (the shift-indexed weight-gradient kernel): a skip
     # concatenation, an upsampled input, 128 output channels
     (4, 8, 16, 32, 32, 32, 3, 0),
@@ -178,6 +187,30 @@ def test_pool_relu_mse_adam(nn):
                                k + 1, None) == 0
         assert float(gd.abs().max()) == 0.0
     assert rel(w.cpu().numpy(), wt.detach().numpy()) < 1e-6
+
+
+@pytest.mark.parametrize("nvox,C,relu", [
+    (999, 8, 1), (1000, 4, 1), (4096, 1, 0), (4096, 1, 1), (512, 128, 1), (64, 1024, 1),
+    (3 << 18, 16, 1),   # 8-element path: C below 8 (folded), shuffled lanes, a two-pass grid-stride loop
+    (105, 1, 1),        # n not a multiple of 8: one element per thread
+    (100, 24, 1),       # C not a power of two
+])
+def test_relu_backward_shapes(nn, nvox, C, relu):
+    lib = nn._lib()
+    rng = np.random.default_rng(nvox + C)
+    n = nvox * C
+    x = _rand(rng, (n,))
+    dout = rng.standard_normal(n).astype(np.float32)
+    xt = nn.to_bf16_tensor(x)
+    g = torch.empty(n, dtype=torch.int16, device="cuda")
+    db = torch.zeros(C, device="cuda")
+    assert lib.ltm_nn_relu_backward(nn._p(torch.from_numpy(dout).cuda()), nn._p(xt) if relu else None, relu,
+                                    nn._p(g), nn._p(db), n, C, None) == 0
+    gref = nn.bf16_round(dout * (x > 0) if relu else dout)
+    assert np.array_equal(nn.from_bf16_tensor(g), gref)
+    gd = gref.reshape(-1, C).astype(np.float64)
+    # FP32 sums in any order: error well under 1e-5 of the sum of magnitudes
+    assert np.all(np.abs(db.cpu().numpy() - gd.sum(0)) <= 1e-5 * np.abs(gd).sum(0) + 1e-30)
 
 
 def _bf16(t):
