@@ -611,20 +611,29 @@ __device__ __forceinline__ void scatter_lds_window(const March& mr, int m0, int 
         atomicAdd(reinterpret_cast<T*>(q + bb), (T)p[2]);
         atomicAdd(reinterpret_cast<T*>(q + bab), (T)p[3]);
     };
-    // the window starts at the first sample's cell
+    // a ray whose dominant coordinate falls (dc < 0) is walked from its last
+    // sample back, so along c the window only ever moves up; the positions
+    // are the same fmaf(m, d, q0) as the forward's, visited in reverse
+    const bool rev = dc < 0.0f;
+    const float finc = rev ? -1.0f : 1.0f;
+    const float fstart = rev ? (float)(m1 - 1) : (float)m0, fend = rev ? (float)(m0 - 1) : (float)m1;
+    // the window starts at the first visited sample's cell
+    float fm = rev ? (float)(m1 - 1 - off) : (float)(m0 + off);
     float fa, fb, fc;
-    int cur = cell((float)(m0 + off), fa, fb, fc);
+    int cur = cell(fm, fa, fb, fc);
     auto step = [&](float fm) {
         const int i0 = cell(fm, fa, fb, fc);
         if (i0 != cur) {
-            const bool up = i0 == cur + sc, down = i0 == cur - sc;
-            if (!down) flush4(cur, lo);
+            // one cell up along c: plane cur is complete and the upper plane
+            // becomes the lower one; any other move (a, b changed, or the
+            // wrap back to the first sample) flushes both planes
+            const bool up = i0 == cur + sc;
+            flush4(cur, lo);
             if (!up) flush4(cur + sc, hi);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const float l = lo[j];
                 lo[j] = up ? hi[j] : 0.0f;
-                hi[j] = down ? l : 0.0f;
+                hi[j] = 0.0f;
             }
             cur = i0;
         }
@@ -637,15 +646,13 @@ __device__ __forceinline__ void scatter_lds_window(const March& mr, int m0, int 
             hi[j] = fmaf(vh, w[j], hi[j]);
         }
     };
-    // the sample index counts in FP32 (exact below 2^24) from m0 + off and
-    // wraps at m1 back to m0: every lane runs cnt iterations, so a wave's
-    // lanes stay busy together
-    float fm = (float)(m0 + off);
-    const float fm0 = (float)m0, fm1 = (float)m1;
+    // the sample index counts in FP32 (exact below 2^24) from the lane's
+    // offset and wraps at the end of [m0, m1) back to its start: every lane
+    // runs cnt iterations, so a wave's lanes stay busy together
     for (int k = 0; k < cnt; ++k) {
         step(fm);
-        fm += 1.0f;
-        fm = fm == fm1 ? fm0 : fm;
+        fm += finc;
+        fm = fm == fend ? fstart : fm;
     }
     if (cnt > 0) {
         flush4(cur, lo);
