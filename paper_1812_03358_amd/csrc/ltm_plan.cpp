@@ -183,11 +183,13 @@ ltm_tiling default_tiling(const ltm_grid& g, const ltm_camera& c, int dir)
         t.order = 1 | 2 | 8 | 32;
         t.chunk_mm = 16.0 * g.pitch_mm;
         t.splits = (uint32_t)std::max<uint64_t>(1, 4 * k / 256);    // 256 pixels per group
+        t.brick_floats = 6144;   // 5 groups per CU (1.51 -> 1.48 ms at 30 deg on 128^3)
     } else if (pl && R <= 4) {
         t.tile_u = t.tile_v = 4;
         t.order = 2 | 8 | 32;
         t.chunk_mm = 32.0 * g.pitch_mm;
         t.splits = (uint32_t)std::max<uint64_t>(1, 16 * k / 256);   // 256 pixels per group
+        t.brick_floats = 6144;   // 5 groups per CU (0.90 -> 0.86 ms on 128^3)
     } else {
         t.tile_u = t.tile_v = 2;
         t.block_u = t.block_v = 8;

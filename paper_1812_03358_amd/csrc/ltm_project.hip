@@ -852,8 +852,11 @@ __device__ void march_tile(const CamDev& c, int tile, const float* __restrict__ 
     __syncthreads();   // the caller may reuse the LDS for the next tile
 }
 
+// Bounded to 5 waves per SIMD (at most 96 VGPRs): with adjoint bricks of up to
+// 6144 floats, 5 workgroups share a CU's LDS, which hides more of the LDS
+// atomics' latency than the few spilled registers cost.
 template <bool kAdj>
-__global__ __launch_bounds__(kThreads, 4) void k_march(CamDev c, const float* __restrict__ in,
+__global__ __launch_bounds__(kThreads, 5) void k_march(CamDev c, const float* __restrict__ in,
                                                     float* __restrict__ yout,
                                                     double* __restrict__ xacc)
 {
@@ -867,7 +870,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_march(CamDev c, const float* __
 // (every workgroup reaches the exit once the counter passes n_items).
 // Items are ordered by decreasing estimated cost.
 template <bool kAdj>
-__global__ __launch_bounds__(kThreads, 4) void k_batch(const BatchCam* __restrict__ cams,
+__global__ __launch_bounds__(kThreads, 5) void k_batch(const BatchCam* __restrict__ cams,
                                                     const uint32_t* __restrict__ items,
                                                     uint32_t n_items,
                                                     unsigned int* __restrict__ counter)

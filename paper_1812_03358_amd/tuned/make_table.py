@@ -7,16 +7,26 @@ tiling, HIP-event timing) and the winners are written to the table, keyed by
 GPU architecture, grid and camera descriptor.  Keys already in the table are
 re-checked, not searched again; delete the file to search afresh.
 
+The 48-frame workload runs as one persistent sweep per direction, launched
+with the largest LDS any member needs, so a camera tuned alone to a larger
+brick or to padded occupancy would lower the workgroups per CU of the whole
+sweep.  Its adjoint tilings are therefore capped at BATCH_BRICK_CAP brick
+floats with no occupancy padding (5 workgroups per CU), each capped tiling
+checked against the searched one through the same parity bar and re-timed.
+
     python -m paper_1812_03358_amd.tuned.make_table [path]
 """
 from __future__ import annotations
 
+import os
 import sys
 import time
 
 import torch
 
 from paper_1812_03358_amd import autotune, ltm, workloads as W
+
+BATCH_BRICK_CAP = 6144
 
 
 def workloads():
@@ -25,13 +35,95 @@ def workloads():
         n = f["grid"]["nx"]
         if n not in seen:
             seen.add(n)
-            yield f"batched_48 frame {n}^3", f["grid"], f["cameras"], W.flame(n, f["volume_seed"])
+            yield f"batched_48 frame {n}^3", f["grid"], f["cameras"], W.flame(n, f["volume_seed"]), True
     cfg = W.config_differentiable()
-    yield "differentiable_256", cfg["grid"], cfg["cameras"], cfg["volume"]()
+    yield "differentiable_256", cfg["grid"], cfg["cameras"], cfg["volume"](), False
+
+
+def _fnv1a(data: bytes, h: int) -> int:
+    for b in data:
+        h = ((h ^ b) * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def table_key(arch: str, g: dict, cam: dict, direction: int) -> str:
+    """The table key ltm_autotune files a camera's tiling under: the readable
+    fields, then FNV-1a (64-bit) over the raw ltm_grid and ltm_camera structs
+    (neither has padding)."""
+    gs = ltm.make_grid(g)
+    cs = ltm.make_cameras([cam])[0]
+    h = _fnv1a(bytes(cs), _fnv1a(bytes(gs), 1469598103934665603))
+    return (f"{arch}|{'A' if direction == ltm.FORWARD else 'AT'}|kind{cs.kind}|grid{gs.nx}x{gs.ny}x{gs.nz}"
+            f"|det{cs.det_nu}x{cs.det_nv}|mla{cs.mla_nu}x{cs.mla_nv}|R{cs.rays_u}x{cs.rays_v}"
+            f"|S{cs.samples}|{h:016x}")
+
+
+def time_adjoint(plan, y, out, reps: int = 5) -> float:
+    plan.backproject(y, out)
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        plan.backproject(y, out)
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return sorted(ts)[len(ts) // 2]
+
+
+FIELDS = ("tile_u", "tile_v", "block_u", "block_v", "order", "splits", "brick_floats", "groups_per_cu",
+          "chunk_mm")
+
+
+def read_table(path: str) -> dict:
+    """key -> tiling dict of every line of a table file."""
+    out = {}
+    if not os.path.exists(path):
+        return out
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        key, tiling = line.rstrip("\n").split("\t")[:2]
+        vals = tiling.split()
+        out[key] = {f: (float(v) if f == "chunk_mm" else int(v)) for f, v in zip(FIELDS, vals)}
+    return out
+
+
+def batch_capped(plan, y, tiling: dict):
+    """A table tiling under the batch cap, parity-checked against the plan's
+    current (tuned) adjoint output and timed; None if it is within the cap."""
+    capped = dict(tiling, brick_floats=min(tiling["brick_floats"], BATCH_BRICK_CAP), groups_per_cu=0)
+    if capped == tiling:
+        return None
+    ref = plan.backproject(y).double()
+    plan.set_tiling(ltm.ADJOINT, 0, capped)
+    out = plan.backproject(y)
+    err = float(torch.linalg.norm(out.double() - ref) / torch.linalg.norm(ref))
+    if not err <= autotune.PARITY:
+        raise RuntimeError(f"capped tiling {capped} fails the parity bar ({err:.2e})")
+    return capped, time_adjoint(plan, y, out)
+
+
+def rewrite(path: str, caps: dict) -> None:
+    """Replace the adjoint tilings of the capped cameras in the table."""
+    lines = open(path).read().splitlines()
+    for i, line in enumerate(lines):
+        if line.startswith("#"):
+            continue
+        key, tiling, times = line.split("\t")
+        if key in caps:
+            t, ms = caps[key]
+            text = " ".join(str(t[f]) for f in FIELDS[:-1])
+            lines[i] = f"{key}\t{text} {t['chunk_mm']!r}\t{ms:.5f} {times.split()[1]}"
+    with open(path + ".tmp", "w") as f:
+        f.write("\n".join(lines) + "\n")
+    os.replace(path + ".tmp", path)
 
 
 def main(path: str) -> None:
-    for name, g, cams, vol in workloads():
+    caps = {}
+    for name, g, cams, vol, batched in workloads():
         x = torch.from_numpy(vol.reshape(-1)).cuda()
         # one camera at a time (the table is keyed per camera and grid)
         for k, cam in enumerate(cams):
@@ -44,6 +136,18 @@ def main(path: str) -> None:
             for r in res:
                 print(f"  {'A ' if r['direction'] == 0 else 'AT'} {r['ms']:.4f} ms "
                       f"(default {r['default_ms']:.4f}) {r['tiling']}", flush=True)
+            if not batched:
+                continue
+            # the table's line decides: the tuner applies it whenever it beats
+            # the default alone
+            key = table_key("gfx950", g, cam, ltm.ADJOINT)
+            filed = read_table(path).get(key)
+            got = batch_capped(plan, y, filed) if filed else None
+            if got is not None:
+                caps[key] = got
+                print(f"  AT {got[1]:.4f} ms under the batch cap {got[0]}", flush=True)
+    if caps:
+        rewrite(path, caps)
 
 
 if __name__ == "__main__":
