@@ -748,6 +748,162 @@ hipError_t wgrad_rows(const ConvWgrad& a, hipStream_t s)
     return hipGetLastError();
 }
 
+// Weight gradient of a 3x3x3 convolution with one input channel (the input
+// layer) on rows of XC (32, 64 or 128) voxels.  With one channel, the 9 input
+// rows (z + dz, y + dy) a unit's taps reach are the columns of one MFMA B
+// operand (9 of 16 used), staged in three copies shifted by dx = -1, 0, 1
+// (zeros outside the grid); the unit's dY of one 16-channel output tile is
+// staged transposed, [co][x].  Each 32 voxels take 3 MFMAs (one per x shift)
+// into D[co][row], tap = row * 3 + d; a wave takes every fourth group of 32
+// voxels, and the workgroup sums its waves in LDS and adds into dw once.
+template <int XC>
+__global__ __launch_bounds__(256) void k_conv_wgrad_c1(ConvWgrad a, int nshare)
+{
+    constexpr int XS = XC + 8;
+    __shared__ __align__(16) u16 xs[3 * 16 * XS];   // [shift][row][x]; rows 9..15 stay zero
+    __shared__ __align__(16) u16 dys[16 * XS];      // [co][x]
+    __shared__ float red[27 * 16];                  // [tap][co]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, kg = lane >> 4;
+    const int cot = blockIdx.x;
+    const int chunks = a.W / XC;
+    const int nunits = a.D * a.H * chunks;
+    const int u0 = (int)(((long long)nunits * blockIdx.y) / nshare);
+    const int u1 = (int)(((long long)nunits * (blockIdx.y + 1)) / nshare);
+    for (int i = threadIdx.x; i < 3 * 16 * XS; i += 256) xs[i] = 0;
+    for (int i = threadIdx.x; i < 27 * 16; i += 256) red[i] = 0.0f;
+    f32x4 acc[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) acc[d] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int unit = u0; unit < u1; ++unit) {
+        const int row = unit / chunks, x0 = (unit - row * chunks) * XC;
+        const int z = row / a.H, y = row - z * a.H;
+        __syncthreads();   // the previous unit's fragments are read (and the clears done)
+        // input halo x0 - 1 + h: copy d (dx = d - 1) holds X[x0 + i + dx] at i = h - d
+        for (int i = threadIdx.x; i < 9 * (XC + 2); i += 256) {
+            const int rr = i / (XC + 2), h = i - rr * (XC + 2);
+            const int zz = z + rr / 3 - 1, yy = y + rr % 3 - 1, x = x0 - 1 + h;
+            u16 v = 0;
+            if ((unsigned)zz < (unsigned)a.D && (unsigned)yy < (unsigned)a.H && (unsigned)x < (unsigned)a.W)
+                v = a.in0[((size_t)zz * a.H + yy) * a.W + x];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int ix = h - d;
+                if ((unsigned)ix < (unsigned)XC) xs[(d * 16 + rr) * XS + ix] = v;
+            }
+        }
+        for (int i = threadIdx.x; i < XC * 2; i += 256) {
+            const int x = i >> 1, half = i & 1;
+            Frag f;
+            f.q = *reinterpret_cast<const uint4*>(a.dy + ((size_t)row * a.W + x0 + x) * a.cout + cot * 16 + half * 8);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) dys[(half * 8 + j) * XS + x] = f.h[j];
+        }
+        __syncthreads();
+        for (int gv = wave * 32; gv < XC; gv += 128) {
+            Frag A;
+            A.q = *reinterpret_cast<const uint4*>(dys + r * XS + gv + 8 * kg);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                Frag B;
+                B.q = *reinterpret_cast<const uint4*>(xs + (d * 16 + r) * XS + gv + 8 * kg);
+                acc[d] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.v, B.v, acc[d], 0, 0, 0);
+            }
+        }
+    }
+    // D[4 kg + i][r]: output channel cot 16 + 4 kg + i, input row r (< 9),
+    // x shift d -> tap r * 3 + d
+    if (r < 9) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (acc[d][i] != 0.0f) atomicAdd(&red[(r * 3 + d) * 16 + 4 * kg + i], acc[d][i]);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 27 * 16; i += 256) {
+        const int tap = i >> 4, co = i & 15;
+        if (red[i] != 0.0f) unsafeAtomicAdd(&a.dw[(size_t)(cot * 16 + co) * a.K + tap], red[i]);
+    }
+}
+
+template <int XC>
+hipError_t wgrad_c1(const ConvWgrad& a, hipStream_t s)
+{
+    const int cot = a.cout / 16;
+    const int units = a.D * a.H * (a.W / XC);
+    // shares of the units until ~1024 workgroups run; each adds 16 x 27 sums
+    const int shares = std::max(1, std::min(units, 1024 / cot));
+    hipLaunchKernelGGL((k_conv_wgrad_c1<XC>), dim3(cot, shares), dim3(256), 0, s, a, shares);
+    return hipGetLastError();
+}
+
+// Weight gradient of a 1x1x1 convolution to one output channel (the output
+// layer): dw[ci] += sum_v dY[v] X[v][ci].  Each thread sums its voxels' CIN
+// channels in registers (16-byte loads), then waves and the workgroup combine
+// them, one atomic per channel and workgroup.
+template <int CIN>
+__global__ __launch_bounds__(256) void k_wgrad_1x1_out1(ConvWgrad a, size_t nvox)
+{
+    __shared__ float red[CIN];
+    if (threadIdx.x < CIN) red[threadIdx.x] = 0.0f;
+    __syncthreads();
+    float sum[CIN];
+#pragma unroll
+    for (int c = 0; c < CIN; ++c) sum[c] = 0.0f;
+    for (size_t v = (size_t)blockIdx.x * 256 + threadIdx.x; v < nvox; v += (size_t)gridDim.x * 256) {
+        const float g = bf2f(a.dy[v]);
+        const u16* x = a.in0 + v * CIN;
+#pragma unroll
+        for (int c8 = 0; c8 < CIN; c8 += 8) {
+            Frag q;
+            q.q = *reinterpret_cast<const uint4*>(x + c8);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sum[c8 + j] = fmaf(g, bf2f(q.h[j]), sum[c8 + j]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CIN; ++c) {
+        float t = sum[c];
+        for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o);
+        if ((threadIdx.x & 63) == 0 && t != 0.0f) atomicAdd(&red[c], t);
+    }
+    __syncthreads();
+    if (threadIdx.x < CIN && red[threadIdx.x] != 0.0f) unsafeAtomicAdd(&a.dw[threadIdx.x], red[threadIdx.x]);
+}
+
+// 1x1x1 convolution to one output channel (the output layer): each voxel's
+// CIN channels (16-byte loads) dotted with the weight row, plus bias, ReLU if
+// asked.
+template <int CIN>
+__global__ __launch_bounds__(256) void k_conv1x1_out1(ConvFwd a, size_t nvox)
+{
+    float w[CIN];
+#pragma unroll
+    for (int c8 = 0; c8 < CIN; c8 += 8) {
+        Frag q;
+        q.q = *reinterpret_cast<const uint4*>(a.wt + c8);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) w[c8 + j] = bf2f(q.h[j]);
+    }
+    const float b = a.bias ? a.bias[0] : 0.0f;
+    for (size_t v = (size_t)blockIdx.x * 256 + threadIdx.x; v < nvox; v += (size_t)gridDim.x * 256) {
+        const u16* x = a.in0 + v * CIN;
+        float acc = 0.0f;
+#pragma unroll
+        for (int c8 = 0; c8 < CIN; c8 += 8) {
+            Frag q;
+            q.q = *reinterpret_cast<const uint4*>(x + c8);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc = fmaf(bf2f(q.h[j]), w[c8 + j], acc);
+        }
+        acc += b;
+        if (a.relu) acc = fmaxf(acc, 0.0f);
+        if (a.out_f32) reinterpret_cast<float*>(a.out)[v] = acc;
+        else reinterpret_cast<u16*>(a.out)[v] = f2bf(acc);
+    }
+}
+
 // ---------------------------------------------------------------- elementwise
 // Pack FP32 master weights [Cout][K] into the BF16 forward layout
 // [NT*16][Kp] and the input-gradient layout [Cin_pad][Kp'] (flipped taps,
@@ -1086,6 +1242,14 @@ hipError_t nn_conv_fwd(const ConvFwd& a, int ks, hipStream_t s)
         }
         return hipGetLastError();
     }
+    if (ks == 1 && a.cout == 1 && a.c1 == 0 && !a.up && (cin == 8 || cin == 16 || cin == 32)) {
+        const size_t nvox = (size_t)a.D * a.H * a.W;
+        const dim3 g(std::min(nblocks(nvox), 4096u));
+        if (cin == 8) hipLaunchKernelGGL((k_conv1x1_out1<8>), g, dim3(256), 0, s, a, nvox);
+        else if (cin == 16) hipLaunchKernelGGL((k_conv1x1_out1<16>), g, dim3(256), 0, s, a, nvox);
+        else hipLaunchKernelGGL((k_conv1x1_out1<32>), g, dim3(256), 0, s, a, nvox);
+        return hipGetLastError();
+    }
     if (ks == 3 && cin1 && a.c1 == 0 && a.cout <= 16) {
         const dim3 g((a.W + 15) / 16, (a.H + 3) / 4, (a.D + 3) / 4);
         hipLaunchKernelGGL(k_conv_fwd_c1, g, dim3(256), 0, s, a);
@@ -1104,6 +1268,19 @@ hipError_t nn_conv_wgrad(const ConvWgrad& a, int ks, hipStream_t s)
         if (xc == 128) return wgrad_rows<128>(a, s);
         if (xc == 64) return wgrad_rows<64>(a, s);
         return wgrad_rows<32>(a, s);
+    }
+    if (ks == 3 && cin == 1 && a.c1 == 0 && !a.up && xc && a.cout % 16 == 0 && a.K == 27) {
+        if (xc == 128) return wgrad_c1<128>(a, s);
+        if (xc == 64) return wgrad_c1<64>(a, s);
+        return wgrad_c1<32>(a, s);
+    }
+    if (ks == 1 && a.cout == 1 && a.c1 == 0 && !a.up && a.K == cin && (cin == 8 || cin == 16 || cin == 32)) {
+        const size_t nvox = (size_t)a.D * a.H * a.W;
+        const dim3 g(std::min(nblocks(nvox), 1024u));
+        if (cin == 8) hipLaunchKernelGGL((k_wgrad_1x1_out1<8>), g, dim3(256), 0, s, a, nvox);
+        else if (cin == 16) hipLaunchKernelGGL((k_wgrad_1x1_out1<16>), g, dim3(256), 0, s, a, nvox);
+        else hipLaunchKernelGGL((k_wgrad_1x1_out1<32>), g, dim3(256), 0, s, a, nvox);
+        return hipGetLastError();
     }
     auto lg2 = [](int n) { int l = 0; while ((1 << l) < n) ++l; return (1 << l) == n ? l : -1; };
     const int lw = lg2(a.W), lh = lg2(a.H);

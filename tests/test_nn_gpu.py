@@ -56,6 +56,14 @@ CASES = [
     (4, 2, 64, 32, 0, 16, 3, 1),
     (3, 2, 64, 24, 8, 16, 3, 0),
     (2, 2, 32, 32, 16, 48, 3, 1),
+    # one input channel on rows of 64, 128 and 32 voxels (weight gradient from
+    # row-shifted copies of the input rows), two output tiles
+    (3, 4, 64, 1, 0, 16, 3, 0),
+    (2, 3, 128, 1, 0, 32, 3, 0),
+    (2, 2, 32, 1, 0, 16, 3, 0),
+    # 1x1x1 to one output channel from 8 and 32 channels
+    (4, 4, 4, 8, 0, 1, 1, 0),
+    (3, 5, 7, 32, 0, 1, 1, 0),
     # power-of-two rows (the shift-indexed weight-gradient kernel): a skip
     # concatenation, an upsampled input, 128 output channels
     (4, 8, 16, 32, 32, 32, 3, 0),
