@@ -247,47 +247,95 @@ __global__ __launch_bounds__(256) void k_conv_fwd_lds(ConvFwd a)
     const u16* abase = hs + (size_t)(((1 * kHY + 1 + wave) * kHX) + 1 + r) * cin;
     const size_t mstride = (size_t)kHY * kHX * cin;
     const u16* bbase = a.wt + (size_t)r * a.Kp + 8 * kg;
-    // two steps per trip with alternating operand buffers: the B fragments
-    // and the offset of the next step are loaded while a step runs its MFMAs;
-    // only the last step can hold K padding, so it alone (peeled) selects
-    auto loadB = [&](Frag (&b)[NT], int ks) {
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-            b[t].q = *reinterpret_cast<const uint4*>(bbase + (size_t)t * 16 * a.Kp + ks * 32);
-    };
-    auto mma = [&](const Frag (&b)[NT], int off, bool pad_step, int ks) {
-        const bool ok = !pad_step || (ks * 32 + 8 * kg) < 27 * cin;
-        Frag A[kTZ];
-#pragma unroll
-        for (int m = 0; m < kTZ; ++m) {
-            A[m].q = *reinterpret_cast<const uint4*>(abase + m * mstride + off);
-            if (pad_step) A[m].q = ok ? A[m].q : uint4{0u, 0u, 0u, 0u};
-        }
-#pragma unroll
-        for (int m = 0; m < kTZ; ++m)
+    if constexpr (NT == 1) {
+        // two steps per trip with alternating operand buffers: the B fragments
+        // and the offset of the next step are loaded while a step runs its MFMAs;
+        // only the last step can hold K padding, so it alone (peeled) selects
+        auto loadB = [&](Frag (&b)[NT], int ks) {
 #pragma unroll
             for (int t = 0; t < NT; ++t)
-                acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[m].v, b[t].v, acc[m][t], 0, 0, 0);
-    };
-    Frag B0[NT], B1[NT];
-    int off0 = koff[kg], off1 = 0;
-    loadB(B0, 0);
-    int ks = 0;
-    for (; ks + 2 < nsteps; ks += 2) {
-        loadB(B1, ks + 1);
-        off1 = koff[(ks + 1) * 4 + kg];
-        mma(B0, off0, false, ks);
-        loadB(B0, ks + 2);
-        off0 = koff[(ks + 2) * 4 + kg];
-        mma(B1, off1, false, ks + 1);
-    }
-    if (ks + 1 < nsteps) {
-        loadB(B1, ks + 1);
-        off1 = koff[(ks + 1) * 4 + kg];
-        mma(B0, off0, false, ks);
-        mma(B1, off1, true, ks + 1);
-    } else if (ks < nsteps) {
-        mma(B0, off0, true, ks);
+                b[t].q = *reinterpret_cast<const uint4*>(bbase + (size_t)t * 16 * a.Kp + ks * 32);
+        };
+        auto mma = [&](const Frag (&b)[NT], int off, bool pad_step, int ks) {
+            const bool ok = !pad_step || (ks * 32 + 8 * kg) < 27 * cin;
+            Frag A[kTZ];
+#pragma unroll
+            for (int m = 0; m < kTZ; ++m) {
+                A[m].q = *reinterpret_cast<const uint4*>(abase + m * mstride + off);
+                if (pad_step) A[m].q = ok ? A[m].q : uint4{0u, 0u, 0u, 0u};
+            }
+#pragma unroll
+            for (int m = 0; m < kTZ; ++m)
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[m].v, b[t].v, acc[m][t], 0, 0, 0);
+        };
+        Frag B0[NT], B1[NT];
+        int off0 = koff[kg], off1 = 0;
+        loadB(B0, 0);
+        int ks = 0;
+        for (; ks + 2 < nsteps; ks += 2) {
+            loadB(B1, ks + 1);
+            off1 = koff[(ks + 1) * 4 + kg];
+            mma(B0, off0, false, ks);
+            loadB(B0, ks + 2);
+            off0 = koff[(ks + 2) * 4 + kg];
+            mma(B1, off1, false, ks + 1);
+        }
+        if (ks + 1 < nsteps) {
+            loadB(B1, ks + 1);
+            off1 = koff[(ks + 1) * 4 + kg];
+            mma(B0, off0, false, ks);
+            mma(B1, off1, true, ks + 1);
+        } else if (ks < nsteps) {
+            mma(B0, off0, true, ks);
+        }
+    } else {
+        // from 2 output tiles on: the weight fragments and halo offsets of the
+        // next P steps are in flight while a step runs its NT x TZ MFMAs, and the
+        // K-padding select runs on every step (one tile: two steps per trip with
+        // alternating buffers and the padding step peeled, faster there --
+        // measured 136 against 147-154 us for the 32-channel 128^3 layers)
+        constexpr int P = NT == 2 ? 3 : 2;
+        auto loadB = [&](Frag (&b)[NT], int ks) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                b[t].q = *reinterpret_cast<const uint4*>(bbase + (size_t)t * 16 * a.Kp + ks * 32);
+        };
+        auto mma = [&](const Frag (&b)[NT], int off, int ks) {
+            const bool ok = ks < nsteps - 1 || (ks * 32 + 8 * kg) < 27 * cin;
+            Frag A[kTZ];
+#pragma unroll
+            for (int m = 0; m < kTZ; ++m) {
+                A[m].q = *reinterpret_cast<const uint4*>(abase + m * mstride + off);
+                A[m].q = ok ? A[m].q : uint4{0u, 0u, 0u, 0u};
+            }
+#pragma unroll
+            for (int m = 0; m < kTZ; ++m)
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[m].v, b[t].v, acc[m][t], 0, 0, 0);
+        };
+        Frag Bq[P][NT];
+        int offq[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            offq[p] = p < nsteps ? koff[p * 4 + kg] : 0;
+            if (p < nsteps) loadB(Bq[p], p);
+        }
+        for (int ks0 = 0; ks0 < nsteps; ks0 += P) {
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int ks = ks0 + p;
+                if (ks < nsteps) {
+                    mma(Bq[p], offq[p], ks);
+                    if (ks + P < nsteps) {
+                        loadB(Bq[p], ks + P);
+                        offq[p] = koff[(ks + P) * 4 + kg];
+                    }
+                }
+            }
+        }
     }
     // epilogue: output row 4 kg + i of tile m is voxel (x0 + 4 kg + i, y0 + wave, z0 + m)
     const int y = y0 + wave;
