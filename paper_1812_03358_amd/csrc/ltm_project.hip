@@ -762,6 +762,25 @@ __device__ void march_tile(const CamDev& c, int tile, const float* __restrict__ 
     __syncthreads();
     const int nrays = t.n_chunks > 0 ? build_ray_list<kAdj>(c, tile, m, wsum) : 0;
 
+    // forward: a lane's ray of the first pass is the same in every slab, so
+    // its set-up (make_ray, exact and slab-independent) is kept in registers
+    // for the whole tile instead of being redone per slab
+    Ray r0;
+    int item0 = 0;
+    if (!kAdj && nrays > 0) {
+        const int parts = nrays >= kThreads ? 1 : kThreads / nrays;
+        if ((int)threadIdx.x < parts * min(nrays, kThreads)) {
+            const int e = parts == 1 ? (int)threadIdx.x : (int)threadIdx.x % nrays;
+            const uint32_t id = m.list[e];
+            item0 = (int)(id & 0xffffu);
+            const int rr = (int)(id >> 16);
+            int iu, iv;
+            item_pixel(c, tile, item0, iu, iv);
+            const int rv = rr / c.ru, ru = rr - rv * c.ru;
+            make_ray(c, iu, iv, ru, rv, r0);
+        }
+    }
+
     for (int ch = 0; ch < t.n_chunks && nrays > 0; ++ch) {
         const BrickRec b = c.bricks[(size_t)tile * c.max_chunks + ch];
         const float za = slab_edge(t, ch, c.chunk);
@@ -794,13 +813,20 @@ __device__ void march_tile(const CamDev& c, int tile, const float* __restrict__ 
             if ((int)threadIdx.x >= parts * min(left, kThreads)) continue;
             const int e = parts == 1 ? e0 + (int)threadIdx.x : e0 + (int)threadIdx.x % left;
             const int part = parts == 1 ? 0 : (int)threadIdx.x / left;
-            const uint32_t id = m.list[e];
-            const int item = (int)(id & 0xffffu), rr = (int)(id >> 16);
-            int iu, iv;
-            item_pixel(c, tile, item, iu, iv);
-            const int rv = rr / c.ru, ru = rr - rv * c.ru;
+            int item;
             Ray r;
-            make_ray(c, iu, iv, ru, rv, r);
+            if (!kAdj && e0 == 0) {
+                item = item0;
+                r = r0;
+            } else {
+                const uint32_t id = m.list[e];
+                item = (int)(id & 0xffffu);
+                const int rr = (int)(id >> 16);
+                int iu, iv;
+                item_pixel(c, tile, item, iu, iv);
+                const int rv = rr / c.ru, ru = rr - rv * c.ru;
+                make_ray(c, iu, iv, ru, rv, r);
+            }
             int m0 = sample_bound(r, za, c.S);
             int m1 = last ? c.S : sample_bound(r, zb, c.S);
             if (parts > 1 && m1 > m0) {
