@@ -762,13 +762,13 @@ __device__ void march_tile(const CamDev& c, int tile, const float* __restrict__ 
     __syncthreads();
     const int nrays = t.n_chunks > 0 ? build_ray_list<kAdj>(c, tile, m, wsum) : 0;
 
-    // forward: a lane's ray of the first pass is the same in every slab, so
-    // its set-up (make_ray, exact and slab-independent) is kept in registers
-    // for the whole tile instead of being redone per slab
+    // a lane's ray of the first pass is the same in every slab, so its
+    // set-up (make_ray, exact and slab-independent) is kept for the whole
+    // tile instead of being redone per slab
     Ray r0;
     int item0 = 0;
-    if (!kAdj && nrays > 0) {
-        const int parts = nrays >= kThreads ? 1 : kThreads / nrays;
+    if (nrays > 0) {
+        const int parts = (kAdj || nrays >= kThreads) ? 1 : kThreads / nrays;
         if ((int)threadIdx.x < parts * min(nrays, kThreads)) {
             const int e = parts == 1 ? (int)threadIdx.x : (int)threadIdx.x % nrays;
             const uint32_t id = m.list[e];
@@ -815,7 +815,7 @@ __device__ void march_tile(const CamDev& c, int tile, const float* __restrict__ 
             const int part = parts == 1 ? 0 : (int)threadIdx.x / left;
             int item;
             Ray r;
-            if (!kAdj && e0 == 0) {
+            if (e0 == 0) {
                 item = item0;
                 r = r0;
             } else {
