@@ -762,22 +762,26 @@ __device__ void march_tile(const CamDev& c, int tile, const float* __restrict__ 
     __syncthreads();
     const int nrays = t.n_chunks > 0 ? build_ray_list<kAdj>(c, tile, m, wsum) : 0;
 
-    // a lane's ray of the first pass is the same in every slab, so its
-    // set-up (make_ray, exact and slab-independent) is kept for the whole
-    // tile instead of being redone per slab
-    Ray r0;
-    int item0 = 0;
-    if (nrays > 0) {
-        const int parts = (kAdj || nrays >= kThreads) ? 1 : kThreads / nrays;
-        if ((int)threadIdx.x < parts * min(nrays, kThreads)) {
-            const int e = parts == 1 ? (int)threadIdx.x : (int)threadIdx.x % nrays;
+    // a lane's rays of the first two passes are the same in every slab, so
+    // their set-up (make_ray, exact and slab-independent) is kept for the
+    // whole tile instead of being redone per slab (later passes, for tiles
+    // of more than 2 x 256 rays, redo it)
+    Ray rp[2];
+    int itemp[2] = {0, 0};
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const int e0 = p * kThreads, left = nrays - e0;
+        if (left <= 0) break;
+        const int parts = (kAdj || left >= kThreads) ? 1 : kThreads / left;
+        if ((int)threadIdx.x < parts * min(left, kThreads)) {
+            const int e = parts == 1 ? e0 + (int)threadIdx.x : e0 + (int)threadIdx.x % left;
             const uint32_t id = m.list[e];
-            item0 = (int)(id & 0xffffu);
+            itemp[p] = (int)(id & 0xffffu);
             const int rr = (int)(id >> 16);
             int iu, iv;
-            item_pixel(c, tile, item0, iu, iv);
+            item_pixel(c, tile, itemp[p], iu, iv);
             const int rv = rr / c.ru, ru = rr - rv * c.ru;
-            make_ray(c, iu, iv, ru, rv, r0);
+            make_ray(c, iu, iv, ru, rv, rp[p]);
         }
     }
 
@@ -816,8 +820,11 @@ __device__ void march_tile(const CamDev& c, int tile, const float* __restrict__ 
             int item;
             Ray r;
             if (e0 == 0) {
-                item = item0;
-                r = r0;
+                item = itemp[0];
+                r = rp[0];
+            } else if (e0 == kThreads) {
+                item = itemp[1];
+                r = rp[1];
             } else {
                 const uint32_t id = m.list[e];
                 item = (int)(id & 0xffffu);
