@@ -347,37 +347,60 @@ __global__ __launch_bounds__(kThreads) void k_setup(CamDev c, TileRec* tiles, Br
 }
 
 // ---------------------------------------------------------------- brick I/O
-__device__ __forceinline__ void brick_coords(int e, int dx, int dy, float inv_dx, float inv_dy,
-                                             int& lx, int& ly, int& lz)
-{
-    // exact for e < 2^20: (e + 1/2)/dx is at least 1/(2 dx) away from an integer
-    const int yz = (int)(((float)e + 0.5f) * inv_dx);
-    lx = e - yz * dx;
-    lz = (int)(((float)yz + 0.5f) * inv_dy);
-    ly = yz - lz * dy;
-}
-
 __device__ __forceinline__ size_t gindex(const int n[3], int x, int y, int z)
 {
     return (size_t)x + (size_t)n[0] * ((size_t)y + (size_t)n[1] * (size_t)z);
 }
 
-// Grid index of a brick voxel, whose coordinates may lie one past the grid:
-// the replicated layer maps onto the edge voxel.
-__device__ __forceinline__ size_t gindex_clamped(const int n[3], int x, int y, int z)
+// Brick words are visited plane by plane.  Lane t owns one point (x, y) of the
+// brick's z-planes and a first plane z0, and steps through z by zq, so that
+// with fewer plane points than lanes the lanes split the planes between them;
+// the point's coordinates and clamped row offset are worked out once, and
+// the z clamp is the same for every lane.  Consecutive lanes read
+// consecutive x.
+struct BrickWalk {
+    int plane, zq, z0, p;
+    size_t off, nxy;   // clamped (x, y) offset and the grid's z stride
+};
+
+// Lanes t < plane * zq take part; exact for t, p < 2^20: (t + 1/2)/d is at
+// least 1/(2 d) away from an integer.
+__device__ __forceinline__ bool brick_walk(const BrickRec& b, const int n[3], int t, BrickWalk& w)
 {
-    return gindex(n, min(max(x, 0), n[0] - 1), min(max(y, 0), n[1] - 1), min(max(z, 0), n[2] - 1));
+    w.plane = b.dim[0] * b.dim[1];
+    w.zq = w.plane >= kThreads ? 1 : kThreads / w.plane;
+    if (t >= w.plane * w.zq) return false;
+    w.z0 = (int)(((float)t + 0.5f) / (float)w.plane);
+    w.p = t - w.z0 * w.plane;
+    const int ly = (int)(((float)w.p + 0.5f) / (float)b.dim[0]), lx = w.p - ly * b.dim[0];
+    const int gx = min(max(b.lo[0] + lx, 0), n[0] - 1), gy = min(max(b.lo[1] + ly, 0), n[1] - 1);
+    w.off = (size_t)gx + (size_t)n[0] * gy;
+    w.nxy = (size_t)n[0] * n[1];
+    return true;
 }
+
+constexpr int kStageLoads = 4;
 
 __device__ void stage_brick(const BrickRec& b, const int n[3], const float* __restrict__ x,
                             float* brick)
 {
-    const int vol = b.dim[0] * b.dim[1] * b.dim[2];
-    const float idx = 1.0f / (float)b.dim[0], idy = 1.0f / (float)b.dim[1];
-    for (int e = threadIdx.x; e < vol; e += kThreads) {
-        int lx, ly, lz;
-        brick_coords(e, b.dim[0], b.dim[1], idx, idy, lx, ly, lz);
-        brick[e] = x[gindex_clamped(n, b.lo[0] + lx, b.lo[1] + ly, b.lo[2] + lz)];
+    for (int t = threadIdx.x;; t += kThreads) {
+        BrickWalk w;
+        if (!brick_walk(b, n, t, w)) break;
+        const float* row = x + w.off;
+        // kStageLoads loads in flight; the clamped z keeps those past the
+        // brick in the grid, and only the brick's planes are stored
+        for (int lz = w.z0; lz < b.dim[2]; lz += kStageLoads * w.zq) {
+            float v[kStageLoads];
+#pragma unroll
+            for (int u = 0; u < kStageLoads; ++u) {
+                const int gz = min(max(b.lo[2] + lz + u * w.zq, 0), n[2] - 1);
+                v[u] = row[w.nxy * gz];
+            }
+#pragma unroll
+            for (int u = 0; u < kStageLoads; ++u)
+                if (lz + u * w.zq < b.dim[2]) brick[w.p + w.plane * (lz + u * w.zq)] = v[u];
+        }
     }
 }
 
@@ -391,14 +414,16 @@ __device__ void zero_brick(const BrickRec& b, T* brick)
 template <typename T>
 __device__ void flush_brick(const BrickRec& b, const int n[3], T* brick, double* __restrict__ x)
 {
-    const int vol = b.dim[0] * b.dim[1] * b.dim[2];
-    const float idx = 1.0f / (float)b.dim[0], idy = 1.0f / (float)b.dim[1];
-    for (int e = threadIdx.x; e < vol; e += kThreads) {
-        const double v = (double)brick[e];
-        if (v == 0.0) continue;
-        int lx, ly, lz;
-        brick_coords(e, b.dim[0], b.dim[1], idx, idy, lx, ly, lz);
-        unsafeAtomicAdd(&x[gindex_clamped(n, b.lo[0] + lx, b.lo[1] + ly, b.lo[2] + lz)], v);
+    for (int t = threadIdx.x;; t += kThreads) {
+        BrickWalk w;
+        if (!brick_walk(b, n, t, w)) break;
+        double* row = x + w.off;
+        for (int lz = w.z0; lz < b.dim[2]; lz += w.zq) {
+            const double v = (double)brick[w.p + w.plane * lz];
+            if (v == 0.0) continue;
+            const int gz = min(max(b.lo[2] + lz, 0), n[2] - 1);
+            unsafeAtomicAdd(&row[w.nxy * gz], v);
+        }
     }
 }
 
