@@ -152,7 +152,7 @@ std::vector<ltm_tiling> shape_candidates(const ltm_grid& g, const ltm_camera& c,
                     if (items % splits || items / splits > 2048 || items / splits * R > 8192) continue;
                     for (uint32_t order : {0u, 2u})
                         for (double chunk : {16.0, 32.0, 64.0})
-                            for (uint32_t brick : {4096u, 8192u}) push(t, blk, order, splits, brick, chunk);
+                            for (uint32_t brick : {4096u, 6144u, 8192u}) push(t, blk, order, splits, brick, chunk);
                 }
             }
     } else {

@@ -10,8 +10,9 @@ re-checked, not searched again; delete the file to search afresh.
 The 48-frame workload runs as one persistent sweep per direction, launched
 with the largest LDS any member needs, so a camera tuned alone to a larger
 brick or to padded occupancy would lower the workgroups per CU of the whole
-sweep.  Its adjoint tilings are therefore capped at BATCH_BRICK_CAP brick
-floats with no occupancy padding (5 workgroups per CU), each capped tiling
+sweep.  Its tilings in both directions are therefore capped at
+BATCH_BRICK_CAP brick floats with no occupancy padding (5 workgroups per CU),
+at the slab depth (full, 1/2 or 1/4) that runs fastest, each capped tiling
 checked against the searched one through the same parity bar and re-timed.
 
     python -m paper_1812_03358_amd.tuned.make_table [path]
@@ -58,14 +59,18 @@ def table_key(arch: str, g: dict, cam: dict, direction: int) -> str:
             f"|S{cs.samples}|{h:016x}")
 
 
-def time_adjoint(plan, y, out, reps: int = 5) -> float:
-    plan.backproject(y, out)
+def _apply(plan, direction: int, x, y, out):
+    return plan.project(x, out) if direction == ltm.FORWARD else plan.backproject(y, out)
+
+
+def time_direction(plan, direction: int, x, y, out, reps: int = 5) -> float:
+    _apply(plan, direction, x, y, out)
     ts = []
     for _ in range(reps):
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record()
-        plan.backproject(y, out)
+        _apply(plan, direction, x, y, out)
         b.record()
         torch.cuda.synchronize()
         ts.append(a.elapsed_time(b))
@@ -90,23 +95,31 @@ def read_table(path: str) -> dict:
     return out
 
 
-def batch_capped(plan, y, tiling: dict):
+def batch_capped(plan, direction: int, x, y, tiling: dict):
     """A table tiling under the batch cap, parity-checked against the plan's
-    current (tuned) adjoint output and timed; None if it is within the cap."""
+    current (tuned) output in that direction and timed.  A smaller brick may
+    not hold the tiling's slabs, which then fall back to global memory, so
+    the slab depth is also tried at 1/2 and 1/4; the fastest is kept (a
+    tiling already within the cap keeps its depth unless a shallower one is
+    faster)."""
     capped = dict(tiling, brick_floats=min(tiling["brick_floats"], BATCH_BRICK_CAP), groups_per_cu=0)
-    if capped == tiling:
-        return None
-    ref = plan.backproject(y).double()
-    plan.set_tiling(ltm.ADJOINT, 0, capped)
-    out = plan.backproject(y)
-    err = float(torch.linalg.norm(out.double() - ref) / torch.linalg.norm(ref))
-    if not err <= autotune.PARITY:
-        raise RuntimeError(f"capped tiling {capped} fails the parity bar ({err:.2e})")
-    return capped, time_adjoint(plan, y, out)
+    ref = _apply(plan, direction, x, y, None).double()
+    best = None
+    for f in (1.0, 0.5, 0.25):
+        t = dict(capped, chunk_mm=capped["chunk_mm"] * f)
+        plan.set_tiling(direction, 0, t)
+        out = _apply(plan, direction, x, y, None)
+        err = float(torch.linalg.norm(out.double() - ref) / torch.linalg.norm(ref))
+        if not err <= autotune.PARITY:
+            raise RuntimeError(f"capped tiling {t} fails the parity bar ({err:.2e})")
+        ms = time_direction(plan, direction, x, y, out)
+        if best is None or ms < best[1]:
+            best = (t, ms)
+    return best
 
 
 def rewrite(path: str, caps: dict) -> None:
-    """Replace the adjoint tilings of the capped cameras in the table."""
+    """Replace the tilings of the capped cameras in the table."""
     lines = open(path).read().splitlines()
     for i, line in enumerate(lines):
         if line.startswith("#"):
@@ -140,12 +153,14 @@ def main(path: str) -> None:
                 continue
             # the table's line decides: the tuner applies it whenever it beats
             # the default alone
-            key = table_key("gfx950", g, cam, ltm.ADJOINT)
-            filed = read_table(path).get(key)
-            got = batch_capped(plan, y, filed) if filed else None
-            if got is not None:
-                caps[key] = got
-                print(f"  AT {got[1]:.4f} ms under the batch cap {got[0]}", flush=True)
+            for d in (ltm.FORWARD, ltm.ADJOINT):
+                key = table_key("gfx950", g, cam, d)
+                filed = read_table(path).get(key)
+                got = batch_capped(plan, d, x, y, filed) if filed else None
+                if got is not None and got[0] != filed:
+                    caps[key] = got
+                    print(f"  {'A ' if d == ltm.FORWARD else 'AT'} {got[1]:.4f} ms under the batch cap {got[0]}",
+                          flush=True)
     if caps:
         rewrite(path, caps)
 

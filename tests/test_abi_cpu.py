@@ -191,7 +191,8 @@ def test_tuned_table_parses():
     if not os.path.exists(autotune.TUNED_TABLE):
         pytest.skip("no tuned table committed")
     from paper_1812_03358_amd.tuned import make_table as M
-    capped = {M.table_key("gfx950", f["grid"], c, 1) for f in W.config_batched() for c in f["cameras"]}
+    capped = {M.table_key("gfx950", f["grid"], c, d) for f in W.config_batched() for c in f["cameras"]
+              for d in (0, 1)}
     rows = [l.rstrip("\n").split("\t") for l in open(autotune.TUNED_TABLE) if not l.startswith("#")]
     assert rows
     for key, tiling, times in rows:
@@ -199,24 +200,25 @@ def test_tuned_table_parses():
         f = tiling.split()
         assert len(f) == 9 and all(v.isdigit() for v in f[:8]) and float(f[8]) > 0
         best, default = map(float, times.split())
-        # a batch-capped adjoint entry may be slower alone than the default
-        assert 0 < best and (best <= default or key in capped)
+        # a batch-capped entry may be slower alone than the default, but not
+        # by much (slabs too deep for the capped brick would fall back to
+        # global memory and run many times slower)
+        assert 0 < best and (best <= default or (key in capped and best <= 1.25 * default))
 
 
 def test_tuned_table_covers_the_batched_workload():
     """Every camera of the 48-frame workload has a table entry in both
-    directions, and its adjoint entry keeps the batch cap (bricks of at most
-    6144 floats, no occupancy padding), so the persistent sweep runs 5
-    workgroups per CU."""
+    directions, and both keep the batch cap (bricks of at most 6144 floats,
+    no occupancy padding), so the persistent sweeps run 5 workgroups per
+    CU."""
     from paper_1812_03358_amd import autotune
     from paper_1812_03358_amd.tuned import make_table as M
     table = M.read_table(autotune.TUNED_TABLE)
     for f in W.config_batched():
         for c in f["cameras"]:
             for d in (0, 1):     # forward, adjoint
-                assert M.table_key("gfx950", f["grid"], c, d) in table
-            t = table[M.table_key("gfx950", f["grid"], c, 1)]
-            assert t["brick_floats"] <= M.BATCH_BRICK_CAP and t["groups_per_cu"] == 0
+                t = table[M.table_key("gfx950", f["grid"], c, d)]
+                assert t["brick_floats"] <= M.BATCH_BRICK_CAP and t["groups_per_cu"] == 0
 
 
 def test_table_key_matches_the_library_hash():
