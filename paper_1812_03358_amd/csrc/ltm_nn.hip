@@ -423,7 +423,6 @@ __global__ __launch_bounds__(256) void k_conv_fwd_c1(ConvFwd a)
         dst[1] = hi.q;
         return;
     }
-#pragma unroll
     for (int co = 0; co < 16; ++co) {
         if (co >= a.cout) break;
         if (co < a.split) {
